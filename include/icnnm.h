@@ -1,0 +1,168 @@
+/*
+ * icnnm.h - C ABI of the MI355X (gfx950) solver for Inductive Convolution
+ * Nuclear Norm Minimization (ICNNM), tensor completion with arbitrary sampling.
+ *
+ * Problem (Definition 1 and eq:InductiveCNNM): given an observed order-n
+ * tensor M (n <= 3; lower orders use unit leading dimensions), a sampling set
+ * Omega given as a mask, a kernel size k_1 x .. x k_n with k_j <= m_j
+ * (Section II-B) and an orthogonal bank V of k convolution eigenvectors
+ * (Section III-A), find
+ *     min_L || A_k(L) V ||_{2,1}   s.t.  P_Omega(L) = P_Omega(M)
+ * or its penalized form (eq:admm) for a finite lambda, by the ADMM iteration of
+ * Section III-D. V is learned beforehand from reference tensors (Definition 3,
+ * eq:A).
+ *
+ * Conventions shared by every entry point
+ *  - Layout: tensors are dense float32 in C order (last dimension fastest);
+ *    vectorisation of tensors and of kernel offsets is C order, so row s of V
+ *    is the kernel offset (s_1, .., s_n) in C order and column i is the i-th
+ *    eigenvector. V is k x k float32, row-major.
+ *  - Omega is a uint8 mask of the tensor's shape: nonzero = observed.
+ *  - Array arguments (M, mask, V, L_out, refs, V_out) are DEVICE pointers on
+ *    the context's device, allocated and owned by the caller. The library
+ *    never frees them and keeps no reference after the call returns (submit:
+ *    until poll reports completion). icnnm_params, icnnm_info, shapes and
+ *    eigvals_out are HOST pointers.
+ *  - stream is a hipStream_t (NULL = the context's own stream). Calls are
+ *    ordered after work already queued on it and return after their outputs
+ *    are written (submit/poll excepted).
+ *  - Errors: every call returns an icnnm_status; on error, nothing is written
+ *    to outputs beyond what is documented and icnnm_last_error() describes the
+ *    failure. No C++ exception crosses this boundary.
+ *  - Thread safety: a context may be used from several host threads; calls
+ *    on one context are serialised internally. icnnm_submit/icnnm_poll may be
+ *    called concurrently with each other.
+ */
+#ifndef ICNNM_H
+#define ICNNM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct icnnm_ctx icnnm_ctx;
+typedef int32_t icnnm_status;
+
+#define ICNNM_OK 0
+#define ICNNM_PENDING 1
+#define ICNNM_E_INVALID (-1)  /* bad shape, pointer or parameter; k_j > m_j; ndim not in [1,3] */
+#define ICNNM_E_NOMEM (-2)    /* device allocation failed */
+#define ICNNM_E_BUDGET (-3)   /* the request alone exceeds the context's HBM budget */
+#define ICNNM_E_DEVICE (-4)   /* HIP runtime error */
+#define ICNNM_E_NUMERIC (-5)  /* NaN/Inf in a residual */
+#define ICNNM_E_NOTFOUND (-6) /* unknown or already collected ticket */
+
+#define ICNNM_PREC_FP32 0
+#define ICNNM_PREC_BF16 1
+#define ICNNM_PREC_FP16 2
+
+/* Shape of one tensor and of its convolution kernel. Only the first ndim
+ * entries of m[] and kdim[] are read; an order-1 or order-2 problem is solved
+ * as an order-3 one with unit leading dimensions (a circular convolution over
+ * a unit dimension is the identity). */
+typedef struct {
+  int32_t ndim;    /* 1..3 */
+  int64_t m[3];    /* tensor dimensions m_1..m_n */
+  int64_t kdim[3]; /* kernel dimensions k_1..k_n, 1 <= k_j <= m_j */
+} icnnm_shape;
+
+/* Solver parameters (Section III-D). Fill with icnnm_params_default first. */
+typedef struct {
+  double lambda;        /* +INFINITY (default): exact P_Omega constraint (eq:InductiveCNNM);
+                           finite > 0: penalized form (eq:admm), lambda = 1000 in the paper */
+  double theta0;        /* initial penalty; <= 0 selects 1.25 / ||A_k(P_Omega M) V||_{2,inf}
+                           (1.0 when that norm is zero) */
+  double rho;           /* penalty growth per iteration, default 1.1 */
+  double theta_max;     /* penalty cap, default 1e10 */
+  int32_t max_iter;     /* iterations to run (default 100) */
+  double tol;           /* stop when max(r_primal, r_change) <= tol; 0 = run max_iter exactly */
+  int32_t precision;    /* ICNNM_PREC_*: arithmetic of the two contractions */
+  int32_t refresh_every;/* reduced precision: full FP32 evaluation every this many iterations */
+  int32_t check_v;      /* nonzero: reject V unless max|V^T V - I| <= 1e-5 */
+} icnnm_params;
+
+/* Per-solve report. r_primal = ||Z - A_k(L)V||_F / (sqrt(k) ||P_Omega M||_F),
+ * r_change = ||L^t - L^{t-1}||_F / ||P_Omega M||_F, objective = ||A_k(L)V||_{2,1}
+ * at the returned L; all reduced in FP64 on the device. */
+typedef struct {
+  int32_t iters;
+  int32_t converged;
+  double r_primal;
+  double r_change;
+  double objective;
+  double theta_final;
+  double t_queue_s;  /* submit only: time from submit to first device work */
+  double t_device_s; /* wall time from first device work to completion */
+} icnnm_info;
+
+/* Default parameters: lambda = +inf, theta0 auto, rho 1.1, theta_max 1e10,
+ * max_iter 100, tol 0, FP32, refresh_every 10, check_v 0. */
+void icnnm_params_default(icnnm_params *p);
+
+/* Create a context on HIP device `device`. hbm_budget_bytes bounds the device
+ * memory the context may hold for solver state (0 = 90% of free memory at
+ * creation). Returns ICNNM_E_DEVICE if the device is not usable. */
+icnnm_status icnnm_create(int device, size_t hbm_budget_bytes, icnnm_ctx **out);
+
+/* Destroy a context: waits for in-flight served requests, frees all state. */
+void icnnm_destroy(icnnm_ctx *ctx);
+
+/* Human-readable description of the last error on this context (never NULL). */
+const char *icnnm_last_error(const icnnm_ctx *ctx);
+
+/* Learn the k convolution eigenvectors of a reference ensemble (Definition 3):
+ * the eigenvectors of sum_j A_k(L_j)^T A_k(L_j) (eq:A), accumulated in FP64 on
+ * the device, all k of them, sorted by descending eigenvalue, each column's
+ * largest-magnitude entry made positive.
+ *   kdim[3]      kernel dimensions, first ref_shapes[0].ndim entries used
+ *   b            number of reference tensors (>= 1)
+ *   ref_shapes   b host shapes; each ref_shapes[j].kdim must equal kdim
+ *   refs         b device pointers to float32 C-order tensors
+ *   V_out        device, k*k float32, row-major [s][i]
+ *   eigvals_out  host, k doubles (descending); may be NULL
+ */
+icnnm_status icnnm_learn_eigvecs(icnnm_ctx *ctx, const int64_t kdim[3], int32_t b,
+                                 const icnnm_shape ref_shapes[], const float *const refs[],
+                                 float *V_out, double *eigvals_out, void *stream);
+
+/* Solve one completion instance (Section III-D iteration).
+ *   shape   host; M, mask, L_out device arrays of prod(m) entries
+ *   V       device, k*k float32 orthogonal eigenvector bank
+ *   L_out   device, receives the final iterate; with lambda = +inf,
+ *           L_out[i] == M[i] bit for bit for every observed i
+ *   info    host, may be NULL
+ */
+icnnm_status icnnm_solve(icnnm_ctx *ctx, const icnnm_shape *shape, const float *M,
+                         const uint8_t *mask, const float *V, const icnnm_params *params,
+                         float *L_out, icnnm_info *info, void *stream);
+
+/* Solve `count` independent instances of possibly different shapes that share
+ * one kernel size and one V, in joint launches (one per stage and iteration,
+ * spanning all instances). Arrays are indexed by instance; infos may be NULL.
+ * Each instance stops on its own when tol > 0. */
+icnnm_status icnnm_solve_batch(icnnm_ctx *ctx, int32_t count, const icnnm_shape shapes[],
+                               const float *const M[], const uint8_t *const masks[],
+                               const float *V, const icnnm_params *params,
+                               float *const L_out[], icnnm_info infos[], void *stream);
+
+/* Serving: enqueue one request and return at once with a ticket. A scheduler
+ * thread admits queued requests while the HBM budget allows, keeps their state
+ * resident, runs all admitted requests sharing a V in joint iterations, and
+ * retires each when its residual meets params->tol (or at max_iter).
+ * Buffers must stay valid until icnnm_poll returns a value other than
+ * ICNNM_PENDING. Returns ICNNM_E_BUDGET if the request can never fit. */
+icnnm_status icnnm_submit(icnnm_ctx *ctx, const icnnm_shape *shape, const float *M,
+                          const uint8_t *mask, const float *V, const icnnm_params *params,
+                          float *L_out, uint64_t *ticket);
+
+/* ICNNM_PENDING while the request runs; its final status once, after which
+ * the ticket is released (a second poll returns ICNNM_E_NOTFOUND). */
+icnnm_status icnnm_poll(icnnm_ctx *ctx, uint64_t ticket, icnnm_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ICNNM_H */

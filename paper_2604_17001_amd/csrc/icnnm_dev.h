@@ -1,0 +1,98 @@
+// Device-side data structures shared by the ICNNM kernels and the host runtime.
+//
+// One ADMM iteration (Section III-D) runs as four stage kernels over a table
+// of spatial tiles that may span many instances:
+//   colnorm : FP64 column norms of Q -> shrink factors s_i (Z-step), penalty
+//             schedule, stopping residuals of the previous iteration
+//   adjoint : G = U + s.Q (scaled Y + theta Z), H = G V^T on MFMA, col2im of H
+//             into an LDS box (transposed convolutions summed back)
+//   lstep   : sums the halo partials of neighbouring tiles, applies the L-step
+//             with P_Omega data consistency
+//   forward : W = A_k(L) V as an implicit-im2col MFMA contraction from an LDS
+//             halo of L, fused with the dual update, next Q and column partials
+// Each instance carries a phase so that instances at different points of
+// their solve (new, initialising, iterating, done) share the same launches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace icnnm {
+
+constexpr int kThreads = 256;  // 4 wavefronts of 64 lanes
+constexpr int kRowUnit = 64;   // spatial rows per wave work unit (two 32-row MFMA groups)
+constexpr int kColUnit = 64;   // columns per wave work unit (two 32-column MFMA blocks)
+constexpr int kGroup = 256;    // columns (forward) or kernel offsets (adjoint) per workgroup
+
+enum Phase : int32_t { kNew = 0, kInit = 1, kRun = 2, kDone = 3 };
+
+enum Prec : int32_t { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
+
+struct alignas(16) InstState {
+  double theta;      // penalty for the next iteration (<= 0: derive theta0 at initialisation)
+  double theta_cur;  // penalty of the iteration in flight
+  double ratio;      // theta_cur / theta_next, rescales the scaled dual U = Y / theta
+  double denom;      // ||P_Omega M||_F, 1 when zero
+  double r_primal;
+  double r_change;
+  double objective;
+  int32_t phase;
+  int32_t iters;
+  int32_t converged;
+  int32_t status;     // 0 ok, -5 numeric
+  uint32_t counter;   // arrival counter of the column-norm reduction (reset by the last block)
+  int32_t refresh;    // reduced precision: this iteration evaluates in FP32
+  int32_t pad[2];
+};
+
+struct alignas(16) InstDev {
+  int32_t m[3], k[3], b[3], E[3], nt[3], C[3], goff[3];
+  int32_t ntiles, bm, E123, nlblk, nslice, lblk0, max_iter, refresh_every;
+  int64_t mtot;
+  double lam, rho, theta_max, tol, theta0;
+  const float* M;
+  const uint8_t* mask;
+  float* L;         // current iterate (C order)
+  float* Lprev;     // reduced precision: iterate at the last forward evaluation
+  float* U;         // scaled dual Y / theta, tile layout
+  float* Q;         // W - U, tile layout
+  float* part;      // adjoint halo partials [ntiles][nsg][E123]
+  float* qpart;     // [ntiles][kp] per-tile sums of Q^2
+  float* wpart;     // [ntiles][kp] per-tile sums of W^2
+  float* rpart;     // [ntiles][ncg] per-tile sums of (Z - W)^2
+  double* dlpart;   // [nlblk] L-step partial sums
+  double* slice;    // [nslice][2 kp + 2] FP64 slice sums of the norm reduction
+  float* s;         // shrink factors [kp]
+  float* T;         // reduced precision: running A_k^*(G V^T) / k  [m]
+  const int32_t* gtab;  // per-dimension gather tables, entries (tile << 16) | position, -1 = none
+  InstState* st;
+};
+
+struct StageArgs {
+  const InstDev* inst;
+  const int2* tiles;     // (instance, local tile) per global tile
+  const int2* lblocks;   // (instance, block) for the L-step
+  const int2* slices;    // (instance, slice) for the column-norm reduction
+  const float* Vf;       // forward operand layout of V (FP32)
+  const float* Va;       // adjoint operand layout of V (FP32)
+  const void* Vf_lo;     // forward operand layout of V (BF16/FP16)
+  const void* Va_lo;     // adjoint operand layout of V (BF16/FP16)
+  int32_t kp, k, nsg, ncg;
+  int32_t tiles_per_slice;
+  int32_t prec;
+};
+
+// Launchers (defined in kernels.hip). All take the stream to launch on.
+void launch_colnorm(const StageArgs& a, int nslices_total, hipStream_t st);
+void launch_adjoint(const StageArgs& a, int ntiles_total, int lds_floats, hipStream_t st);
+void launch_lstep(const StageArgs& a, int nlblocks_total, hipStream_t st);
+void launch_forward(const StageArgs& a, int ntiles_total, int lds_floats, hipStream_t st);
+void launch_prep_v(const float* V, int k, int kp, float* Vf, float* Va, void* Vf_lo,
+                   void* Va_lo, int prec, hipStream_t st);
+void launch_check_v(const float* V, int k, float* out_maxdev, hipStream_t st);
+void launch_autocorr(const float* L, const int32_t* m, const int32_t* k, double* R,
+                     hipStream_t st);
+void launch_gram_expand(const double* R, const int32_t* k, double* G, hipStream_t st);
+void launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t st);
+
+}  // namespace icnnm

@@ -1,0 +1,1052 @@
+// Host runtime of the ICNNM library: contexts, HBM budget, tile planning, the
+// phase-driven group executor shared by solve / solve_batch / serving, the
+// eigenvector learning pre-step and the C ABI of include/icnnm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/icnnm.h"
+#include "icnnm_dev.h"
+
+namespace icnnm {
+
+void sym_eig(std::vector<double>& A, int n, std::vector<double>& w, std::vector<double>& V);
+
+struct Error : std::runtime_error {
+  icnnm_status code;
+  Error(icnnm_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCK(expr)                                                                                  \
+  do {                                                                                               \
+    hipError_t e_ = (expr);                                                                          \
+    if (e_ != hipSuccess)                                                                            \
+      throw Error(ICNNM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));               \
+  } while (0)
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------------------------ memory budget
+struct Budget {
+  size_t limit = 0;
+  std::atomic<size_t> used{0};
+  void* alloc(size_t bytes) {
+    if (bytes == 0) return nullptr;
+    size_t cur = used.load();
+    do {
+      if (cur + bytes > limit) throw Error(ICNNM_E_BUDGET, "HBM budget exhausted");
+    } while (!used.compare_exchange_weak(cur, cur + bytes));
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      used -= bytes;
+      (void)hipGetLastError();
+      throw Error(ICNNM_E_NOMEM, "hipMalloc failed for " + std::to_string(bytes) + " bytes");
+    }
+    return p;
+  }
+  void release(void* p, size_t bytes) {
+    if (!p) return;
+    (void)hipFree(p);
+    used -= bytes;
+  }
+};
+
+struct DevBuf {
+  Budget* b = nullptr;
+  void* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { reset(); }
+  void reset() {
+    if (p && b) b->release(p, n);
+    p = nullptr;
+    n = 0;
+  }
+  void ensure(Budget* bud, size_t bytes) {
+    if (bytes <= n && p) return;
+    reset();
+    b = bud;
+    p = bud->alloc(bytes);
+    n = bytes;
+  }
+  template <class T>
+  T* as() const {
+    return reinterpret_cast<T*>(p);
+  }
+};
+
+// ------------------------------------------------------------------------------ planning
+struct Plan {
+  int m[3], k[3], b[3], E[3], nt[3], C[3], goff[3];
+  int ntiles, bm, E123, nlblk, nslice;
+  int64_t mtot;
+  std::vector<int32_t> gtab;
+  size_t state_floats() const;
+};
+
+constexpr int kTilesPerSlice = 16;
+
+static int pow2ceil(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+static int lds_forward_floats(const Plan& p, int kp) {
+  const int CG = std::min(kp, kGroup);
+  const int nrc = p.bm / kRowUnit, ncc = CG / kColUnit;
+  return p.E123 + kp + 2 * nrc * CG + nrc * ncc;
+}
+
+static int lds_adjoint_floats(const Plan& p, int kp) { return p.E123 + kp; }
+
+static Plan make_plan(const int m[3], const int k[3], int kp) {
+  Plan best{};
+  double best_cost = 1e300;
+  const int nsg = (kp + kGroup - 1) / kGroup;
+  for (int bm : {64, 128, 256, 512}) {
+    for (int b2 = 1; b2 <= std::min(pow2ceil(m[2]), bm); b2 <<= 1) {
+      for (int b1 = 1; b1 * b2 <= bm && b1 <= pow2ceil(m[1]); b1 <<= 1) {
+        const int b0 = bm / (b1 * b2);
+        if (b0 * b1 * b2 != bm || b0 > pow2ceil(m[0])) continue;
+        Plan p{};
+        for (int d = 0; d < 3; ++d) {
+          p.m[d] = m[d];
+          p.k[d] = k[d];
+        }
+        p.b[0] = b0;
+        p.b[1] = b1;
+        p.b[2] = b2;
+        p.bm = bm;
+        int64_t ntiles = 1;
+        for (int d = 0; d < 3; ++d) {
+          p.E[d] = p.b[d] + k[d] - 1;
+          p.nt[d] = (m[d] + p.b[d] - 1) / p.b[d];
+          ntiles *= p.nt[d];
+        }
+        p.E123 = p.E[0] * p.E[1] * p.E[2];
+        p.ntiles = (int)ntiles;
+        if (lds_forward_floats(p, kp) * 4 > 150 * 1024) continue;
+        if (p.E[0] > 65535 || p.E[1] > 65535 || p.E[2] > 65535 || ntiles > 65535 * 16) continue;
+        const double mt = (double)m[0] * m[1] * m[2];
+        const double padded = (double)ntiles * bm / mt;
+        const double halo = (double)p.E123 * nsg / (2.0 * bm * kp);
+        const double wgs = (double)ntiles * nsg;
+        const double occ = wgs >= 2048 ? 1.0 : 1.0 + 0.5 * (2048 - wgs) / 2048;
+        const double cost = padded * (1.0 + halo) * occ;
+        if (cost < best_cost - 1e-12) {
+          best_cost = cost;
+          best = p;
+        }
+      }
+    }
+  }
+  if (best_cost >= 1e300) throw Error(ICNNM_E_INVALID, "no tile shape fits this problem");
+  Plan& p = best;
+  p.mtot = (int64_t)m[0] * m[1] * m[2];
+  p.nlblk = (int)((p.mtot + kThreads - 1) / kThreads);
+  p.nslice = (p.ntiles + kTilesPerSlice - 1) / kTilesPerSlice;
+  // gather tables: for each coordinate t of dimension d, the (tile, box position) pairs
+  // whose box position (n b - (k - 1) + p) mod m equals t
+  int off = 0;
+  for (int d = 0; d < 3; ++d) {
+    std::vector<std::vector<int32_t>> lists(m[d]);
+    for (int n = 0; n < p.nt[d]; ++n)
+      for (int q = 0; q < p.E[d]; ++q) {
+        int t = n * p.b[d] - (k[d] - 1) + q;
+        t %= m[d];
+        if (t < 0) t += m[d];
+        lists[t].push_back((n << 16) | q);
+      }
+    int C = 0;
+    for (auto& l : lists) C = std::max<int>(C, (int)l.size());
+    p.C[d] = C;
+    p.goff[d] = off;
+    for (auto& l : lists) {
+      for (int c = 0; c < C; ++c) p.gtab.push_back(c < (int)l.size() ? l[c] : -1);
+    }
+    off += m[d] * C;
+  }
+  return best;
+}
+
+// ------------------------------------------------------------------------------ group executor
+// One solve state: the device arrays of one instance.
+struct Member {
+  Plan plan;
+  icnnm_params params;
+  const float* M = nullptr;
+  const uint8_t* mask = nullptr;
+  float* Lout = nullptr;
+  DevBuf buf;     // all per-instance state, carved below
+  InstDev dev{};  // host copy of the descriptor
+  int slot = -1;  // index into the group's InstState array
+  // serving bookkeeping
+  uint64_t ticket = 0;
+  double t_submit = 0, t_start = 0;
+};
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// padded kernel size: a multiple of the 64-column wave unit, and of the 256-column
+// workgroup group once k exceeds one group
+static int padded_k(int k) { return k <= kGroup ? (k + 63) / 64 * 64 : (k + kGroup - 1) / kGroup * kGroup; }
+
+static size_t member_bytes(const Plan& p, int kp, int nsg, int ncg, int prec) {
+  size_t b = 0;
+  const size_t st = (size_t)p.ntiles * p.bm * kp;
+  b += 2 * align256(st * 4);                                // U, Q
+  b += align256((size_t)p.ntiles * nsg * p.E123 * 4);        // part
+  b += 2 * align256((size_t)p.ntiles * kp * 4);              // qpart, wpart
+  b += align256((size_t)p.ntiles * ncg * 4);                 // rpart
+  b += align256((size_t)p.nlblk * 8);                        // dlpart
+  b += align256((size_t)p.nslice * (2 * kp + 2) * 8);        // slice
+  b += align256((size_t)kp * 4);                             // s
+  b += align256(p.gtab.size() * 4);                          // gather tables
+  if (prec != kFP32) b += 2 * align256((size_t)p.mtot * 4);  // Lprev, T
+  return b;
+}
+
+struct Group {
+  Budget* budget;
+  int kd[3];
+  int k, kp, nsg, ncg, prec;
+  const float* Vsrc = nullptr;
+  DevBuf Vf, Va, Vlo_f, Vlo_a;
+  std::vector<Member*> members;
+  int capacity;
+  DevBuf states;  // InstState[capacity]
+  std::vector<int> free_slots;
+  DevBuf inst, tiles, lblocks, slices;
+  int ntiles_total = 0, nlblk_total = 0, nslice_total = 0, lds_fwd = 0, lds_adj = 0;
+  bool dirty = true;
+  hipGraphExec_t gexec = nullptr;
+  int graph_rounds = 0;
+
+  Group(Budget* b, const int kdim[3], int prec_, int cap) : budget(b), prec(prec_), capacity(cap) {
+    for (int d = 0; d < 3; ++d) kd[d] = kdim[d];
+    k = kd[0] * kd[1] * kd[2];
+    kp = padded_k(k);
+    nsg = (kp + kGroup - 1) / kGroup;
+    ncg = nsg;
+    states.ensure(budget, sizeof(InstState) * capacity);
+    for (int i = capacity - 1; i >= 0; --i) free_slots.push_back(i);
+  }
+  ~Group() { drop_graph(); }
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+    graph_rounds = 0;
+  }
+
+  void set_v(const float* V, hipStream_t st) {
+    Vsrc = V;
+    const size_t n = (size_t)kp * kp;
+    Vf.ensure(budget, n * 4);
+    Va.ensure(budget, n * 4);
+    launch_prep_v(V, k, kp, Vf.as<float>(), Va.as<float>(), nullptr, nullptr, prec, st);
+    HIPCK(hipGetLastError());
+  }
+
+  InstState* state_ptr(int slot) const { return states.as<InstState>() + slot; }
+
+  // carve a member's device arrays and fill its descriptor
+  void attach(Member* mb, hipStream_t st) {
+    if (free_slots.empty()) throw Error(ICNNM_E_BUDGET, "no free slot in group");
+    const Plan& p = mb->plan;
+    mb->buf.ensure(budget, member_bytes(p, kp, nsg, ncg, prec));
+    char* base = mb->buf.as<char>();
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      void* q = base + off;
+      off += align256(bytes);
+      return q;
+    };
+    InstDev& d = mb->dev;
+    d = InstDev{};
+    for (int i = 0; i < 3; ++i) {
+      d.m[i] = p.m[i];
+      d.k[i] = p.k[i];
+      d.b[i] = p.b[i];
+      d.E[i] = p.E[i];
+      d.nt[i] = p.nt[i];
+      d.C[i] = p.C[i];
+      d.goff[i] = p.goff[i];
+    }
+    d.ntiles = p.ntiles;
+    d.bm = p.bm;
+    d.E123 = p.E123;
+    d.nlblk = p.nlblk;
+    d.nslice = p.nslice;
+    d.mtot = p.mtot;
+    d.max_iter = mb->params.max_iter;
+    d.refresh_every = mb->params.refresh_every;
+    d.lam = std::isinf(mb->params.lambda) ? 1e308 : mb->params.lambda;
+    d.rho = mb->params.rho;
+    d.theta_max = mb->params.theta_max;
+    d.tol = mb->params.tol;
+    d.theta0 = mb->params.theta0;
+    d.M = mb->M;
+    d.mask = mb->mask;
+    d.L = mb->Lout;
+    const size_t stf = (size_t)p.ntiles * p.bm * kp;
+    d.U = (float*)take(stf * 4);
+    d.Q = (float*)take(stf * 4);
+    d.part = (float*)take((size_t)p.ntiles * nsg * p.E123 * 4);
+    d.qpart = (float*)take((size_t)p.ntiles * kp * 4);
+    d.wpart = (float*)take((size_t)p.ntiles * kp * 4);
+    d.rpart = (float*)take((size_t)p.ntiles * ncg * 4);
+    d.dlpart = (double*)take((size_t)p.nlblk * 8);
+    d.slice = (double*)take((size_t)p.nslice * (2 * kp + 2) * 8);
+    d.s = (float*)take((size_t)kp * 4);
+    int32_t* gt = (int32_t*)take(p.gtab.size() * 4);
+    d.gtab = gt;
+    if (prec != kFP32) {
+      d.Lprev = (float*)take((size_t)p.mtot * 4);
+      d.T = (float*)take((size_t)p.mtot * 4);
+    }
+    HIPCK(hipMemcpyAsync(gt, p.gtab.data(), p.gtab.size() * 4, hipMemcpyHostToDevice, st));
+    mb->slot = free_slots.back();
+    free_slots.pop_back();
+    d.st = state_ptr(mb->slot);
+    InstState s0{};
+    s0.theta = mb->params.theta0 > 0 ? mb->params.theta0 : -1.0;
+    s0.phase = kNew;
+    HIPCK(hipMemcpyAsync(d.st, &s0, sizeof(s0), hipMemcpyHostToDevice, st));
+    HIPCK(hipStreamSynchronize(st));  // the host sources above are short-lived
+    members.push_back(mb);
+    dirty = true;
+  }
+
+  void detach(Member* mb) {
+    auto it = std::find(members.begin(), members.end(), mb);
+    if (it != members.end()) members.erase(it);
+    if (mb->slot >= 0) free_slots.push_back(mb->slot);
+    mb->slot = -1;
+    mb->buf.reset();
+    dirty = true;
+  }
+
+  // rebuild the descriptor array and the tile / L-step / slice tables
+  void rebuild(hipStream_t st) {
+    std::vector<InstDev> ds;
+    std::vector<int2> tl, lb, sl;
+    lds_fwd = lds_adj = 0;
+    for (size_t i = 0; i < members.size(); ++i) {
+      const Member* mb = members[i];
+      ds.push_back(mb->dev);
+      for (int t = 0; t < mb->plan.ntiles; ++t) tl.push_back(make_int2((int)i, t));
+      for (int t = 0; t < mb->plan.nlblk; ++t) lb.push_back(make_int2((int)i, t));
+      for (int t = 0; t < mb->plan.nslice; ++t) sl.push_back(make_int2((int)i, t));
+      lds_fwd = std::max(lds_fwd, lds_forward_floats(mb->plan, kp));
+      lds_adj = std::max(lds_adj, lds_adjoint_floats(mb->plan, kp));
+    }
+    ntiles_total = (int)tl.size();
+    nlblk_total = (int)lb.size();
+    nslice_total = (int)sl.size();
+    auto up = [&](DevBuf& b, const void* src, size_t bytes) {
+      if (bytes == 0) return;
+      if (bytes > b.n) {
+        // keep the old buffer until queued work that reads it has finished
+        HIPCK(hipStreamSynchronize(st));
+        b.ensure(budget, bytes * 2);
+      }
+      HIPCK(hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, st));
+    };
+    up(inst, ds.data(), ds.size() * sizeof(InstDev));
+    up(tiles, tl.data(), tl.size() * sizeof(int2));
+    up(lblocks, lb.data(), lb.size() * sizeof(int2));
+    up(slices, sl.data(), sl.size() * sizeof(int2));
+    HIPCK(hipStreamSynchronize(st));  // host tables go out of scope
+    drop_graph();
+    dirty = false;
+  }
+
+  StageArgs args() const {
+    StageArgs a{};
+    a.inst = inst.as<InstDev>();
+    a.tiles = tiles.as<int2>();
+    a.lblocks = lblocks.as<int2>();
+    a.slices = slices.as<int2>();
+    a.Vf = Vf.as<float>();
+    a.Va = Va.as<float>();
+    a.Vf_lo = Vlo_f.p;
+    a.Va_lo = Vlo_a.p;
+    a.kp = kp;
+    a.k = k;
+    a.nsg = nsg;
+    a.ncg = ncg;
+    a.tiles_per_slice = kTilesPerSlice;
+    a.prec = prec;
+    return a;
+  }
+
+  void launch_round(hipStream_t st) {
+    const StageArgs a = args();
+    launch_colnorm(a, nslice_total, st);
+    launch_adjoint(a, ntiles_total, lds_adj, st);
+    launch_lstep(a, nlblk_total, st);
+    launch_forward(a, ntiles_total, lds_fwd, st);
+  }
+
+  // run `rounds` rounds, replaying a captured graph of `chunk` rounds when asked
+  void run(int rounds, hipStream_t st, bool use_graph, int chunk) {
+    if (dirty) rebuild(st);
+    if (members.empty() || rounds <= 0) return;
+    if (!use_graph) {
+      for (int r = 0; r < rounds; ++r) launch_round(st);
+      HIPCK(hipGetLastError());
+      return;
+    }
+    chunk = std::max(1, std::min(chunk, rounds));
+    if (!gexec || graph_rounds != chunk) {
+      drop_graph();
+      hipGraph_t g;
+      HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      for (int r = 0; r < chunk; ++r) launch_round(st);
+      HIPCK(hipStreamEndCapture(st, &g));
+      HIPCK(hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0));
+      HIPCK(hipGraphDestroy(g));
+      graph_rounds = chunk;
+    }
+    int done = 0;
+    while (done + chunk <= rounds) {
+      HIPCK(hipGraphLaunch(gexec, st));
+      done += chunk;
+    }
+    for (; done < rounds; ++done) launch_round(st);
+    HIPCK(hipGetLastError());
+  }
+
+  void read_states(std::vector<InstState>& out, hipStream_t st) {
+    out.resize(capacity);
+    HIPCK(hipMemcpyAsync(out.data(), states.p, sizeof(InstState) * capacity, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+  }
+};
+
+static void fill_info(const InstState& s, icnnm_info* info) {
+  if (!info) return;
+  info->iters = s.iters;
+  info->converged = s.converged;
+  info->r_primal = s.r_primal;
+  info->r_change = s.r_change;
+  info->objective = s.objective;
+  info->theta_final = s.theta;
+}
+
+// ------------------------------------------------------------------------------ context
+struct Request {
+  uint64_t ticket;
+  icnnm_shape shape;
+  int m[3], kd[3];
+  const float* M;
+  const uint8_t* mask;
+  const float* V;
+  icnnm_params params;
+  float* Lout;
+  double t_submit;
+  size_t bytes;
+};
+
+struct Done {
+  icnnm_status status;
+  icnnm_info info;
+};
+
+}  // namespace icnnm
+
+struct icnnm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  icnnm::Budget budget;
+  std::recursive_mutex mu;  // serialises synchronous calls
+  std::string last_error;
+  std::mutex err_mu;
+  // cached single-instance groups keyed by (shape, kernel, precision)
+  std::map<std::string, std::unique_ptr<icnnm::Group>> cache;
+  std::map<std::string, std::unique_ptr<icnnm::Member>> cache_members;
+  // serving
+  std::mutex q_mu;
+  std::condition_variable q_cv;
+  std::deque<icnnm::Request> queue;
+  std::map<uint64_t, icnnm::Done> done;
+  std::map<uint64_t, int> pending;  // 1 = queued or running
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  std::thread server;
+  hipStream_t serve_stream = nullptr;
+};
+
+namespace icnnm {
+
+static void set_error(icnnm_ctx* c, const std::string& m) {
+  if (!c) return;
+  std::lock_guard<std::mutex> g(c->err_mu);
+  c->last_error = m;
+}
+
+template <class F>
+static icnnm_status guarded(icnnm_ctx* c, F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    set_error(c, e.what());
+    return e.code;
+  } catch (const std::exception& e) {
+    set_error(c, e.what());
+    return ICNNM_E_DEVICE;
+  } catch (...) {
+    set_error(c, "unknown error");
+    return ICNNM_E_DEVICE;
+  }
+}
+
+static void normalize_shape(const icnnm_shape* s, int m[3], int kd[3]) {
+  if (!s) throw Error(ICNNM_E_INVALID, "shape is NULL");
+  if (s->ndim < 1 || s->ndim > 3) throw Error(ICNNM_E_INVALID, "ndim must be 1, 2 or 3");
+  const int lead = 3 - s->ndim;
+  for (int d = 0; d < 3; ++d) {
+    m[d] = 1;
+    kd[d] = 1;
+  }
+  for (int d = 0; d < s->ndim; ++d) {
+    if (s->m[d] < 1 || s->m[d] > (1 << 24)) throw Error(ICNNM_E_INVALID, "tensor dimension out of range");
+    if (s->kdim[d] < 1 || s->kdim[d] > s->m[d])
+      throw Error(ICNNM_E_INVALID, "kernel dimension must satisfy 1 <= k_j <= m_j");
+    m[lead + d] = (int)s->m[d];
+    kd[lead + d] = (int)s->kdim[d];
+  }
+  const int64_t mt = (int64_t)m[0] * m[1] * m[2];
+  if (mt > ((int64_t)1 << 31) - 1) throw Error(ICNNM_E_INVALID, "tensor too large");
+  const int64_t k = (int64_t)kd[0] * kd[1] * kd[2];
+  if (k > 4096) throw Error(ICNNM_E_INVALID, "kernel size k above 4096 is not supported");
+}
+
+static void check_params(const icnnm_params* p) {
+  if (!p) throw Error(ICNNM_E_INVALID, "params is NULL");
+  if (!(p->lambda > 0)) throw Error(ICNNM_E_INVALID, "lambda must be > 0 (or +inf)");
+  if (!(p->rho >= 1.0) || !(p->theta_max > 0)) throw Error(ICNNM_E_INVALID, "rho must be >= 1, theta_max > 0");
+  if (p->max_iter < 0) throw Error(ICNNM_E_INVALID, "max_iter must be >= 0");
+  if (!(p->tol >= 0)) throw Error(ICNNM_E_INVALID, "tol must be >= 0");
+  if (p->precision < 0 || p->precision > 2) throw Error(ICNNM_E_INVALID, "unknown precision");
+  if (p->precision != 0) throw Error(ICNNM_E_INVALID, "reduced precision is not built in this library yet");
+}
+
+static void check_v(icnnm_ctx* c, const float* V, int k, hipStream_t st) {
+  float* dv = nullptr;
+  HIPCK(hipMallocAsync((void**)&dv, 4, st));
+  HIPCK(hipMemsetAsync(dv, 0, 4, st));
+  launch_check_v(V, k, dv, st);
+  float h = 0;
+  HIPCK(hipMemcpyAsync(&h, dv, 4, hipMemcpyDeviceToHost, st));
+  HIPCK(hipFreeAsync(dv, st));
+  HIPCK(hipStreamSynchronize(st));
+  if (!(h <= 1e-5f)) throw Error(ICNNM_E_INVALID, "V is not orthogonal: max|V^T V - I| = " + std::to_string(h));
+  (void)c;
+}
+
+// order the context stream after the caller's stream
+static hipStream_t enter(icnnm_ctx* c, void* user) {
+  hipStream_t us = (hipStream_t)user;
+  if (us && us != c->stream) {
+    HIPCK(hipEventRecord(c->ev_in, us));
+    HIPCK(hipStreamWaitEvent(c->stream, c->ev_in, 0));
+  }
+  return c->stream;
+}
+
+static void leave(icnnm_ctx* c, void* user) {
+  hipStream_t us = (hipStream_t)user;
+  if (us && us != c->stream) {
+    HIPCK(hipEventRecord(c->ev_out, c->stream));
+    HIPCK(hipStreamWaitEvent(us, c->ev_out, 0));
+  }
+  HIPCK(hipStreamSynchronize(c->stream));
+}
+
+static std::string key_of(const int m[3], const int kd[3], const icnnm_params* p) {
+  char buf[256];
+  snprintf(buf, sizeof buf, "%d,%d,%d|%d,%d,%d|%d", m[0], m[1], m[2], kd[0], kd[1], kd[2], p->precision);
+  return buf;
+}
+
+static icnnm_status do_solve(icnnm_ctx* c, const icnnm_shape* shape, const float* M, const uint8_t* mask,
+                             const float* V, const icnnm_params* params, float* L_out, icnnm_info* info,
+                             void* user_stream) {
+  int m[3], kd[3];
+  normalize_shape(shape, m, kd);
+  check_params(params);
+  if (!M || !mask || !V || !L_out) throw Error(ICNNM_E_INVALID, "NULL array argument");
+  std::lock_guard<std::recursive_mutex> lock(c->mu);
+  hipStream_t st = enter(c, user_stream);
+  const int k = kd[0] * kd[1] * kd[2];
+  if (params->check_v) check_v(c, V, k, st);
+  const std::string key = key_of(m, kd, params);
+  auto it = c->cache.find(key);
+  Group* g;
+  Member* mb;
+  if (it == c->cache.end()) {
+    auto grp = std::make_unique<Group>(&c->budget, kd, params->precision, 1);
+    auto mem = std::make_unique<Member>();
+    mem->plan = make_plan(m, kd, grp->kp);
+    mem->params = *params;
+    mem->M = M;
+    mem->mask = mask;
+    mem->Lout = L_out;
+    grp->attach(mem.get(), st);
+    g = grp.get();
+    mb = mem.get();
+    c->cache[key] = std::move(grp);
+    c->cache_members[key] = std::move(mem);
+  } else {
+    g = it->second.get();
+    mb = c->cache_members[key].get();
+    // re-point the descriptor at this call's arrays and reset the state
+    mb->params = *params;
+    mb->M = M;
+    mb->mask = mask;
+    mb->Lout = L_out;
+    InstDev& d = mb->dev;
+    d.M = M;
+    d.mask = mask;
+    d.L = L_out;
+    d.max_iter = params->max_iter;
+    d.refresh_every = params->refresh_every;
+    d.lam = std::isinf(params->lambda) ? 1e308 : params->lambda;
+    d.rho = params->rho;
+    d.theta_max = params->theta_max;
+    d.tol = params->tol;
+    d.theta0 = params->theta0;
+    InstState s0{};
+    s0.theta = params->theta0 > 0 ? params->theta0 : -1.0;
+    s0.phase = kNew;
+    HIPCK(hipMemcpyAsync(d.st, &s0, sizeof(s0), hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(g->inst.p, &d, sizeof(InstDev), hipMemcpyHostToDevice, st));
+    HIPCK(hipStreamSynchronize(st));
+  }
+  g->set_v(V, st);
+  const double t0 = now_s();
+  const int total = params->max_iter + 2;  // new -> init, init -> first iteration, final reduction
+  if (params->tol > 0) {
+    int ran = 0;
+    std::vector<InstState> sts;
+    while (ran < total) {
+      const int chunk = std::min(10, total - ran);
+      g->run(chunk, st, true, 10);
+      ran += chunk;
+      g->read_states(sts, st);
+      if (sts[mb->slot].phase == kDone) break;
+    }
+  } else {
+    g->run(total, st, true, std::min(total, 16));
+  }
+  std::vector<InstState> sts;
+  g->read_states(sts, st);
+  leave(c, user_stream);
+  const InstState& s = sts[mb->slot];
+  if (info) {
+    fill_info(s, info);
+    info->t_queue_s = 0;
+    info->t_device_s = now_s() - t0;
+  }
+  if (s.phase != kDone) throw Error(ICNNM_E_DEVICE, "solver did not reach its final state");
+  if (s.status != 0) {
+    set_error(c, "NaN or Inf in a residual");
+    return ICNNM_E_NUMERIC;
+  }
+  return ICNNM_OK;
+}
+
+static icnnm_status do_solve_batch(icnnm_ctx* c, int count, const icnnm_shape* shapes, const float* const* Ms,
+                                   const uint8_t* const* masks, const float* V, const icnnm_params* params,
+                                   float* const* Louts, icnnm_info* infos, void* user_stream) {
+  if (count < 0 || (count > 0 && (!shapes || !Ms || !masks || !Louts || !V)))
+    throw Error(ICNNM_E_INVALID, "bad batch arguments");
+  check_params(params);
+  if (count == 0) return ICNNM_OK;
+  int kd0[3];
+  std::vector<std::unique_ptr<Member>> mems;
+  for (int i = 0; i < count; ++i) {
+    int m[3], kd[3];
+    normalize_shape(&shapes[i], m, kd);
+    if (i == 0) std::copy(kd, kd + 3, kd0);
+    if (!std::equal(kd, kd + 3, kd0)) throw Error(ICNNM_E_INVALID, "batch instances must share the kernel size");
+    if (!Ms[i] || !masks[i] || !Louts[i]) throw Error(ICNNM_E_INVALID, "NULL array in batch");
+    auto mb = std::make_unique<Member>();
+    mb->params = *params;
+    mb->M = Ms[i];
+    mb->mask = masks[i];
+    mb->Lout = Louts[i];
+    mems.push_back(std::move(mb));
+    (void)m;
+  }
+  std::lock_guard<std::recursive_mutex> lock(c->mu);
+  hipStream_t st = enter(c, user_stream);
+  Group g(&c->budget, kd0, params->precision, count);
+  if (params->check_v) check_v(c, V, g.k, st);
+  for (int i = 0; i < count; ++i) {
+    int m[3], kd[3];
+    normalize_shape(&shapes[i], m, kd);
+    mems[i]->plan = make_plan(m, kd, g.kp);
+    g.attach(mems[i].get(), st);
+  }
+  g.set_v(V, st);
+  const double t0 = now_s();
+  const int total = params->max_iter + 2;
+  if (params->tol > 0) {
+    int ran = 0;
+    std::vector<InstState> sts;
+    while (ran < total) {
+      const int chunk = std::min(10, total - ran);
+      g.run(chunk, st, true, 10);
+      ran += chunk;
+      g.read_states(sts, st);
+      bool all = true;
+      for (auto& mb : mems) all = all && sts[mb->slot].phase == kDone;
+      if (all) break;
+    }
+  } else {
+    g.run(total, st, true, std::min(total, 16));
+  }
+  std::vector<InstState> sts;
+  g.read_states(sts, st);
+  leave(c, user_stream);
+  icnnm_status rc = ICNNM_OK;
+  for (int i = 0; i < count; ++i) {
+    const InstState& s = sts[mems[i]->slot];
+    if (infos) {
+      fill_info(s, &infos[i]);
+      infos[i].t_queue_s = 0;
+      infos[i].t_device_s = now_s() - t0;
+    }
+    if (s.status != 0) rc = ICNNM_E_NUMERIC;
+    if (s.phase != kDone) rc = ICNNM_E_DEVICE;
+  }
+  for (auto& mb : mems) g.detach(mb.get());
+  if (rc != ICNNM_OK) set_error(c, "one or more batch instances failed");
+  return rc;
+}
+
+// ------------------------------------------------------------------------------ learning
+static icnnm_status do_learn(icnnm_ctx* c, const int64_t kdim_in[3], int b, const icnnm_shape* shapes,
+                             const float* const* refs, float* V_out, double* eig_out, void* user_stream) {
+  if (b < 1 || !shapes || !refs || !V_out || !kdim_in) throw Error(ICNNM_E_INVALID, "bad learn arguments");
+  const int nd = shapes[0].ndim;
+  icnnm_shape ks = shapes[0];
+  for (int d = 0; d < nd; ++d) ks.kdim[d] = kdim_in[d];
+  int m0[3], kd[3];
+  normalize_shape(&ks, m0, kd);
+  const int k = kd[0] * kd[1] * kd[2];
+  std::lock_guard<std::recursive_mutex> lock(c->mu);
+  hipStream_t st = enter(c, user_stream);
+  const int ndiff = (2 * kd[0] - 1) * (2 * kd[1] - 1) * (2 * kd[2] - 1);
+  DevBuf R, G;
+  R.ensure(&c->budget, (size_t)ndiff * 8);
+  G.ensure(&c->budget, (size_t)k * k * 8);
+  HIPCK(hipMemsetAsync(R.p, 0, (size_t)ndiff * 8, st));
+  for (int j = 0; j < b; ++j) {
+    icnnm_shape sj = shapes[j];
+    if (sj.ndim != nd) throw Error(ICNNM_E_INVALID, "reference tensors must share the order");
+    for (int d = 0; d < nd; ++d) sj.kdim[d] = kdim_in[d];
+    int m[3], kk[3];
+    normalize_shape(&sj, m, kk);
+    if (!refs[j]) throw Error(ICNNM_E_INVALID, "NULL reference");
+    launch_autocorr(refs[j], m, kd, R.as<double>(), st);
+  }
+  launch_gram_expand(R.as<double>(), kd, G.as<double>(), st);
+  HIPCK(hipGetLastError());
+  std::vector<double> Gh((size_t)k * k);
+  HIPCK(hipMemcpyAsync(Gh.data(), G.p, Gh.size() * 8, hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  std::vector<double> w, Vd;
+  sym_eig(Gh, k, w, Vd);
+  std::vector<float> Vf(Vd.size());
+  for (size_t i = 0; i < Vd.size(); ++i) Vf[i] = (float)Vd[i];
+  HIPCK(hipMemcpyAsync(V_out, Vf.data(), Vf.size() * 4, hipMemcpyHostToDevice, st));
+  leave(c, user_stream);
+  if (eig_out) std::copy(w.begin(), w.end(), eig_out);
+  return ICNNM_OK;
+}
+
+}  // namespace icnnm
+
+// ================================================================================ C ABI
+using namespace icnnm;
+
+extern "C" {
+
+void icnnm_params_default(icnnm_params* p) {
+  if (!p) return;
+  p->lambda = INFINITY;
+  p->theta0 = 0.0;
+  p->rho = 1.1;
+  p->theta_max = 1e10;
+  p->max_iter = 100;
+  p->tol = 0.0;
+  p->precision = ICNNM_PREC_FP32;
+  p->refresh_every = 10;
+  p->check_v = 0;
+}
+
+icnnm_status icnnm_create(int device, size_t hbm_budget_bytes, icnnm_ctx** out) {
+  if (!out) return ICNNM_E_INVALID;
+  *out = nullptr;
+  auto* c = new (std::nothrow) icnnm_ctx();
+  if (!c) return ICNNM_E_NOMEM;
+  icnnm_status rc = guarded(c, [&]() -> icnnm_status {
+    int n = 0;
+    HIPCK(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) throw Error(ICNNM_E_DEVICE, "no such HIP device");
+    HIPCK(hipSetDevice(device));
+    c->device = device;
+    HIPCK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    HIPCK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+    HIPCK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+    size_t fr = 0, tot = 0;
+    HIPCK(hipMemGetInfo(&fr, &tot));
+    c->budget.limit = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
+    return ICNNM_OK;
+  });
+  if (rc != ICNNM_OK) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return ICNNM_OK;
+}
+
+void icnnm_destroy(icnnm_ctx* c);
+
+const char* icnnm_last_error(const icnnm_ctx* c) {
+  if (!c) return "NULL context";
+  return c->last_error.c_str();
+}
+
+icnnm_status icnnm_learn_eigvecs(icnnm_ctx* c, const int64_t kdim[3], int32_t b, const icnnm_shape ref_shapes[],
+                                 const float* const refs[], float* V_out, double* eigvals_out, void* stream) {
+  if (!c) return ICNNM_E_INVALID;
+  return guarded(c, [&] { return do_learn(c, kdim, b, ref_shapes, refs, V_out, eigvals_out, stream); });
+}
+
+icnnm_status icnnm_solve(icnnm_ctx* c, const icnnm_shape* shape, const float* M, const uint8_t* mask,
+                         const float* V, const icnnm_params* params, float* L_out, icnnm_info* info,
+                         void* stream) {
+  if (!c) return ICNNM_E_INVALID;
+  return guarded(c, [&] { return do_solve(c, shape, M, mask, V, params, L_out, info, stream); });
+}
+
+icnnm_status icnnm_solve_batch(icnnm_ctx* c, int32_t count, const icnnm_shape shapes[], const float* const M[],
+                               const uint8_t* const masks[], const float* V, const icnnm_params* params,
+                               float* const L_out[], icnnm_info infos[], void* stream) {
+  if (!c) return ICNNM_E_INVALID;
+  return guarded(c, [&] { return do_solve_batch(c, count, shapes, M, masks, V, params, L_out, infos, stream); });
+}
+
+}  // extern "C"
+
+// ================================================================================ serving
+namespace icnnm {
+
+struct ServeGroup {
+  std::unique_ptr<Group> g;
+  std::vector<std::unique_ptr<Member>> active;
+};
+
+static std::string group_key(const float* V, const int kd[3], int prec) {
+  char buf[160];
+  snprintf(buf, sizeof buf, "%p|%d,%d,%d|%d", (const void*)V, kd[0], kd[1], kd[2], prec);
+  return buf;
+}
+
+constexpr int kServeSlots = 512;
+constexpr int kServeRounds = 4;
+
+// Continuous batching: admit queued requests while the HBM budget allows, run all
+// admitted requests of a (V, kernel, precision) group in joint launches, retire
+// finished ones after each chunk of rounds.
+static void serve_loop(icnnm_ctx* c) {
+  (void)hipSetDevice(c->device);
+  std::map<std::string, ServeGroup> groups;
+  std::vector<InstState> sts;
+  hipStream_t st = c->serve_stream;
+  for (;;) {
+    std::vector<Request> admit;
+    {
+      std::unique_lock<std::mutex> lk(c->q_mu);
+      bool any_active = false;
+      for (auto& kv : groups) any_active = any_active || !kv.second.active.empty();
+      if (!any_active) c->q_cv.wait(lk, [&] { return c->stop || !c->queue.empty(); });
+      if (c->stop && c->queue.empty() && !any_active) break;
+      // FIFO admission against the budget (state bytes were computed at submit)
+      while (!c->queue.empty()) {
+        Request& r = c->queue.front();
+        if (c->budget.used.load() + r.bytes > c->budget.limit) break;
+        admit.push_back(r);
+        c->queue.pop_front();
+      }
+    }
+    for (Request& r : admit) {
+      icnnm_status rc = guarded(c, [&]() -> icnnm_status {
+        const std::string key = group_key(r.V, r.kd, r.params.precision);
+        ServeGroup& sg = groups[key];
+        if (!sg.g) {
+          sg.g = std::make_unique<Group>(&c->budget, r.kd, r.params.precision, kServeSlots);
+          sg.g->set_v(r.V, st);
+        }
+        auto mb = std::make_unique<Member>();
+        mb->plan = make_plan(r.m, r.kd, sg.g->kp);
+        mb->params = r.params;
+        mb->M = r.M;
+        mb->mask = r.mask;
+        mb->Lout = r.Lout;
+        mb->ticket = r.ticket;
+        mb->t_submit = r.t_submit;
+        mb->t_start = now_s();
+        sg.g->attach(mb.get(), st);
+        sg.active.push_back(std::move(mb));
+        return ICNNM_OK;
+      });
+      if (rc != ICNNM_OK) {
+        std::lock_guard<std::mutex> lk(c->q_mu);
+        Done d{};
+        d.status = rc;
+        c->done[r.ticket] = d;
+        c->pending.erase(r.ticket);
+      }
+    }
+    for (auto it = groups.begin(); it != groups.end();) {
+      ServeGroup& sg = it->second;
+      if (sg.active.empty()) {
+        it = groups.erase(it);
+        continue;
+      }
+      icnnm_status rc = guarded(c, [&]() -> icnnm_status {
+        sg.g->run(kServeRounds, st, true, kServeRounds);
+        sg.g->read_states(sts, st);
+        return ICNNM_OK;
+      });
+      std::vector<std::unique_ptr<Member>> keep;
+      for (auto& mb : sg.active) {
+        const InstState& s = sts[mb->slot];
+        if (rc == ICNNM_OK && s.phase != kDone) {
+          keep.push_back(std::move(mb));
+          continue;
+        }
+        Done d{};
+        d.status = rc != ICNNM_OK ? rc : (s.status != 0 ? ICNNM_E_NUMERIC : ICNNM_OK);
+        fill_info(s, &d.info);
+        const double t = now_s();
+        d.info.t_queue_s = mb->t_start - mb->t_submit;
+        d.info.t_device_s = t - mb->t_start;
+        sg.g->detach(mb.get());
+        std::lock_guard<std::mutex> lk(c->q_mu);
+        c->done[mb->ticket] = d;
+        c->pending.erase(mb->ticket);
+      }
+      sg.active = std::move(keep);
+      ++it;
+    }
+  }
+}
+
+static icnnm_status do_submit(icnnm_ctx* c, const icnnm_shape* shape, const float* M, const uint8_t* mask,
+                              const float* V, const icnnm_params* params, float* L_out, uint64_t* ticket) {
+  if (!ticket) throw Error(ICNNM_E_INVALID, "ticket is NULL");
+  Request r{};
+  normalize_shape(shape, r.m, r.kd);
+  check_params(params);
+  if (!M || !mask || !V || !L_out) throw Error(ICNNM_E_INVALID, "NULL array argument");
+  r.shape = *shape;
+  r.M = M;
+  r.mask = mask;
+  r.V = V;
+  r.params = *params;
+  r.Lout = L_out;
+  r.t_submit = now_s();
+  const int k = r.kd[0] * r.kd[1] * r.kd[2];
+  const int kp = padded_k(k);
+  const int nsg = (kp + kGroup - 1) / kGroup;
+  const Plan p = make_plan(r.m, r.kd, kp);
+  r.bytes = member_bytes(p, kp, nsg, nsg, params->precision);
+  if (r.bytes + (size_t)kp * kp * 8 + sizeof(InstState) * kServeSlots > c->budget.limit)
+    throw Error(ICNNM_E_BUDGET, "request alone exceeds the HBM budget");
+  std::lock_guard<std::mutex> lk(c->q_mu);
+  if (!c->server.joinable()) {
+    HIPCK(hipStreamCreateWithFlags(&c->serve_stream, hipStreamNonBlocking));
+    c->server = std::thread(serve_loop, c);
+  }
+  r.ticket = c->next_ticket++;
+  c->pending[r.ticket] = 1;
+  c->queue.push_back(r);
+  *ticket = r.ticket;
+  c->q_cv.notify_one();
+  return ICNNM_OK;
+}
+
+static icnnm_status do_poll(icnnm_ctx* c, uint64_t ticket, icnnm_info* info) {
+  std::lock_guard<std::mutex> lk(c->q_mu);
+  if (c->pending.count(ticket)) return ICNNM_PENDING;
+  auto it = c->done.find(ticket);
+  if (it == c->done.end()) throw Error(ICNNM_E_NOTFOUND, "unknown ticket");
+  if (info) *info = it->second.info;
+  const icnnm_status rc = it->second.status;
+  c->done.erase(it);
+  return rc;
+}
+
+}  // namespace icnnm
+
+extern "C" {
+
+icnnm_status icnnm_submit(icnnm_ctx* c, const icnnm_shape* shape, const float* M, const uint8_t* mask,
+                          const float* V, const icnnm_params* params, float* L_out, uint64_t* ticket) {
+  if (!c) return ICNNM_E_INVALID;
+  return guarded(c, [&] { return do_submit(c, shape, M, mask, V, params, L_out, ticket); });
+}
+
+icnnm_status icnnm_poll(icnnm_ctx* c, uint64_t ticket, icnnm_info* info) {
+  if (!c) return ICNNM_E_INVALID;
+  return guarded(c, [&] { return do_poll(c, ticket, info); });
+}
+
+void icnnm_destroy(icnnm_ctx* c) {
+  if (!c) return;
+  {
+    std::lock_guard<std::mutex> lk(c->q_mu);
+    c->stop = true;
+  }
+  c->q_cv.notify_all();
+  if (c->server.joinable()) c->server.join();
+  {
+    std::lock_guard<std::recursive_mutex> lock(c->mu);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    c->cache_members.clear();
+    c->cache.clear();
+  }
+  if (c->serve_stream) (void)hipStreamDestroy(c->serve_stream);
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,150 @@
+"""Benchmark of the ICNNM solver on one MI355X.
+
+A step is one complete solve (every ADMM iteration of Section III-D: column
+norms and shrinkage, adjoint with col2im, L-step with P_Omega, forward
+contraction with the fused dual update) of one synthetic tensor. The default
+workload is the 64x64x16 video-shaped tensor with an 8x8x4 kernel (k = 256),
+30% random plus 8x8 block missing entries, 200 iterations, FP32. The metric
+is solved tensors per second with inputs resident in HBM.
+
+Prints one JSON line with the throughput, per-solve latency percentiles, the
+relative error against the stored FP64 oracle result, a roofline entry for
+the dominant kernel (stage durations measured with HIP events on the
+library's stream in a separate profiled pass) and the FP64 oracle's own rate
+on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS = {"fp32_mfma": 157.3, "bf16_mfma": 2500.0, "fp16_mfma": 2500.0, "hbm_gbs": 8000.0}
+
+
+def _workload(name):
+    from paper_2604_17001_amd import inputs
+    return {"c1": inputs.c1_plain, "c2": inputs.c2_plain, "c3": inputs.c3_precision}[name]()
+
+
+def _cpu_baseline(prob, V, kdims, iters, sample_iters):
+    """The FP64 oracle, untuned, on `sample_iters` iterations of the same solve."""
+    from oracle import icnnm_ref as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count()
+    t0 = time.perf_counter()
+    O.solve(prob.M, prob.mask, V.astype(np.float64), kdims, sample_iters)
+    dt = time.perf_counter() - t0
+    per_iter = dt / sample_iters
+    return {"value": 1.0 / (per_iter * iters), "unit": "tensors/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{sample_iters} of {iters} iterations of one solve ({dt:.1f} s), scaled to a full solve"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--cpu-sample-iters", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "independent instances shard across GPUs without communication", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2604_17001_amd import icnnm
+
+    wl = _workload(args.workload)
+    prob = wl.problems[0]
+    kd = wl.kdims
+    m, k = prob.m, prob.k
+    lib = icnnm.Library.get()
+    dev = torch.device("cuda", 0)
+    M = torch.from_numpy(prob.M).to(dev)
+    mask = torch.from_numpy(prob.mask).to(dev)
+    refs = [torch.from_numpy(r).to(dev) for r in wl.refs]
+    V, _ = lib.learn_eigvecs(refs, kd)          # pre-step, not timed
+    L = torch.empty_like(M)
+    kw = dict(max_iter=wl.iters, precision=args.precision)
+
+    for _ in range(args.warmup):
+        lib.solve(M, mask, V, kd, out=L, **kw)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        _, info = lib.solve(M, mask, V, kd, out=L, **kw)
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = args.steps / dt
+
+    # accuracy against the stored FP64 oracle result (same float32 V)
+    rel_err = None
+    gV = os.path.join(ROOT, "tests", "golden", f"{args.workload}_V.npy")
+    gL = os.path.join(ROOT, "tests", "golden", f"{args.workload}_L.npy")
+    if os.path.exists(gV) and os.path.exists(gL):
+        Vg = torch.from_numpy(np.load(gV)).to(dev)
+        Lg, _ = lib.solve(M, mask, Vg, kd, **kw)
+        ref = np.load(gL)
+        rel_err = float(np.linalg.norm(Lg.cpu().numpy().astype(np.float64) - ref) / np.linalg.norm(ref))
+
+    # stage durations with HIP events on the library stream (separate profiled pass)
+    roofline, stages = None, None
+    if not args.no_profile:
+        lib.stage_times(reset=True)
+        lib.set_profiling(True)
+        nprof = 2
+        for _ in range(nprof):
+            lib.solve(M, mask, V, kd, out=L, **kw)
+        lib.set_profiling(False)
+        st = lib.stage_times(reset=True)
+        working = {"colnorm": wl.iters + 1, "adjoint": wl.iters, "lstep": wl.iters + 1, "forward": wl.iters + 1}
+        stages = {s: {"avg_us": 1e3 * ms / (nprof * working[s]), "launches": n} for s, (ms, n) in st.items()}
+        dom = max(("forward", "adjoint"), key=lambda s: stages[s]["avg_us"])
+        flops = 2.0 * m * k * k          # one m x k x k contraction per launch
+        achieved = flops / (stages[dom]["avg_us"] * 1e-6) / 1e12
+        peak = PEAKS["fp32_mfma"] if args.precision == "fp32" else PEAKS[f"{args.precision}_mfma"]
+        roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
+                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                    "flops_per_launch": flops}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = _cpu_baseline(prob, V.cpu().numpy(), kd, wl.iters, args.cpu_sample_iters)
+
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": "solved tensors/s at rel.err<=1e-5 (FP32) vs FP64 oracle",
+        "value": round(value, 3), "unit": "tensors/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else args.precision,
+        "data": "synthetic",
+        "config": {"workload": wl.name, "dims": list(prob.dims), "kdims": list(kd), "k": k,
+                   "iters": wl.iters, "precision": args.precision, "lambda": "inf"},
+        "p50_ms": round(float(np.percentile(lat_ms, 50)), 3), "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+        "iter_us": round(1e3 * dt / args.steps / wl.iters * 1e3, 2),
+        "rel_err_vs_oracle": rel_err, "iters_run": info["iters"],
+        "roofline": roofline, "stages": stages, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -162,6 +162,17 @@ icnnm_status icnnm_submit(icnnm_ctx *ctx, const icnnm_shape *shape, const float 
  * the ticket is released (a second poll returns ICNNM_E_NOTFOUND). */
 icnnm_status icnnm_poll(icnnm_ctx *ctx, uint64_t ticket, icnnm_info *info);
 
+/* Stage timing for measurement. While enabled on a context, synchronous solves
+ * launch their stage kernels one by one (no graph replay) with a pair of HIP
+ * events around each launch on the context's stream; the elapsed times are
+ * accumulated per stage. Stages: 0 column norms, 1 adjoint, 2 L-step,
+ * 3 forward. icnnm_stage_times copies the totals (milliseconds) and launch
+ * counts into the host arrays ms[4] and counts[4], then resets them if reset
+ * is nonzero. Timing adds event overhead between launches; keep it off for
+ * throughput runs. */
+icnnm_status icnnm_set_profiling(icnnm_ctx *ctx, int32_t enable);
+icnnm_status icnnm_stage_times(icnnm_ctx *ctx, double ms[4], int64_t counts[4], int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

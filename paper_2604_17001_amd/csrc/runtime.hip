@@ -239,6 +239,14 @@ struct Group {
   bool dirty = true;
   hipGraphExec_t gexec = nullptr;
   int graph_rounds = 0;
+  // stage timing (events around each launch) when profiling is on
+  struct Prof {
+    bool on = false;
+    double ms[4] = {0, 0, 0, 0};
+    int64_t n[4] = {0, 0, 0, 0};
+    std::vector<hipEvent_t> ev;
+  };
+  Prof* prof = nullptr;
 
   Group(Budget* b, const int kdim[3], int prec_, int cap) : budget(b), prec(prec_), capacity(cap) {
     for (int d = 0; d < 3; ++d) kd[d] = kdim[d];
@@ -249,7 +257,7 @@ struct Group {
     states.ensure(budget, sizeof(InstState) * capacity);
     for (int i = capacity - 1; i >= 0; --i) free_slots.push_back(i);
   }
-  ~Group() { drop_graph(); }
+  ~Group() { drop_graph(); }  // prof belongs to the context
   void drop_graph() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     gexec = nullptr;
@@ -406,10 +414,43 @@ struct Group {
     launch_forward(a, ntiles_total, lds_fwd, st);
   }
 
+  // one round with an event pair around each stage; returns after the events are read
+  void launch_round_timed(hipStream_t st) {
+    const StageArgs a = args();
+    if (prof->ev.empty()) {
+      prof->ev.resize(8);
+      for (auto& e : prof->ev) HIPCK(hipEventCreate(&e));
+    }
+    HIPCK(hipEventRecord(prof->ev[0], st));
+    launch_colnorm(a, nslice_total, st);
+    HIPCK(hipEventRecord(prof->ev[1], st));
+    HIPCK(hipEventRecord(prof->ev[2], st));
+    launch_adjoint(a, ntiles_total, lds_adj, st);
+    HIPCK(hipEventRecord(prof->ev[3], st));
+    HIPCK(hipEventRecord(prof->ev[4], st));
+    launch_lstep(a, nlblk_total, st);
+    HIPCK(hipEventRecord(prof->ev[5], st));
+    HIPCK(hipEventRecord(prof->ev[6], st));
+    launch_forward(a, ntiles_total, lds_fwd, st);
+    HIPCK(hipEventRecord(prof->ev[7], st));
+    HIPCK(hipEventSynchronize(prof->ev[7]));
+    for (int i = 0; i < 4; ++i) {
+      float t = 0;
+      HIPCK(hipEventElapsedTime(&t, prof->ev[2 * i], prof->ev[2 * i + 1]));
+      prof->ms[i] += t;
+      prof->n[i] += 1;
+    }
+  }
+
   // run `rounds` rounds, replaying a captured graph of `chunk` rounds when asked
   void run(int rounds, hipStream_t st, bool use_graph, int chunk) {
     if (dirty) rebuild(st);
     if (members.empty() || rounds <= 0) return;
+    if (prof && prof->on) {
+      for (int r = 0; r < rounds; ++r) launch_round_timed(st);
+      HIPCK(hipGetLastError());
+      return;
+    }
     if (!use_graph) {
       for (int r = 0; r < rounds; ++r) launch_round(st);
       HIPCK(hipGetLastError());
@@ -494,6 +535,7 @@ struct icnnm_ctx {
   bool stop = false;
   std::thread server;
   hipStream_t serve_stream = nullptr;
+  icnnm::Group::Prof prof;  // stage timing of synchronous calls
 };
 
 namespace icnnm {
@@ -644,6 +686,7 @@ static icnnm_status do_solve(icnnm_ctx* c, const icnnm_shape* shape, const float
     HIPCK(hipStreamSynchronize(st));
   }
   g->set_v(V, st);
+  g->prof = &c->prof;
   const double t0 = now_s();
   const int total = params->max_iter + 2;  // new -> init, init -> first iteration, final reduction
   if (params->tol > 0) {
@@ -710,6 +753,7 @@ static icnnm_status do_solve_batch(icnnm_ctx* c, int count, const icnnm_shape* s
     g.attach(mems[i].get(), st);
   }
   g.set_v(V, st);
+  g.prof = &c->prof;
   const double t0 = now_s();
   const int total = params->max_iter + 2;
   if (params->tol > 0) {
@@ -742,6 +786,7 @@ static icnnm_status do_solve_batch(icnnm_ctx* c, int count, const icnnm_shape* s
     if (s.phase != kDone) rc = ICNNM_E_DEVICE;
   }
   for (auto& mb : mems) g.detach(mb.get());
+  g.prof = nullptr;
   if (rc != ICNNM_OK) set_error(c, "one or more batch instances failed");
   return rc;
 }
@@ -1028,6 +1073,27 @@ icnnm_status icnnm_poll(icnnm_ctx* c, uint64_t ticket, icnnm_info* info) {
   return guarded(c, [&] { return do_poll(c, ticket, info); });
 }
 
+icnnm_status icnnm_set_profiling(icnnm_ctx* c, int32_t enable) {
+  if (!c) return ICNNM_E_INVALID;
+  std::lock_guard<std::recursive_mutex> lock(c->mu);
+  c->prof.on = enable != 0;
+  return ICNNM_OK;
+}
+
+icnnm_status icnnm_stage_times(icnnm_ctx* c, double ms[4], int64_t counts[4], int32_t reset) {
+  if (!c || !ms || !counts) return ICNNM_E_INVALID;
+  std::lock_guard<std::recursive_mutex> lock(c->mu);
+  for (int i = 0; i < 4; ++i) {
+    ms[i] = c->prof.ms[i];
+    counts[i] = c->prof.n[i];
+    if (reset) {
+      c->prof.ms[i] = 0;
+      c->prof.n[i] = 0;
+    }
+  }
+  return ICNNM_OK;
+}
+
 void icnnm_destroy(icnnm_ctx* c) {
   if (!c) return;
   {
@@ -1041,6 +1107,8 @@ void icnnm_destroy(icnnm_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     c->cache_members.clear();
     c->cache.clear();
+    for (auto& e : c->prof.ev) (void)hipEventDestroy(e);
+    c->prof.ev.clear();
   }
   if (c->serve_stream) (void)hipStreamDestroy(c->serve_stream);
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);

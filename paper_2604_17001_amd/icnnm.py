@@ -23,7 +23,9 @@ E_INVALID, E_NOMEM, E_BUDGET, E_DEVICE, E_NUMERIC, E_NOTFOUND = -1, -2, -3, -4, 
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
 
 EXPORTS = ["icnnm_params_default", "icnnm_create", "icnnm_destroy", "icnnm_last_error",
-           "icnnm_learn_eigvecs", "icnnm_solve", "icnnm_solve_batch", "icnnm_submit", "icnnm_poll"]
+           "icnnm_learn_eigvecs", "icnnm_solve", "icnnm_solve_batch", "icnnm_submit", "icnnm_poll",
+           "icnnm_set_profiling", "icnnm_stage_times"]
+STAGES = ("colnorm", "adjoint", "lstep", "forward")
 
 
 class Shape(C.Structure):
@@ -77,6 +79,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.icnnm_submit.restype = C.c_int32
     lib.icnnm_poll.argtypes = [P, C.c_uint64, C.POINTER(Info)]
     lib.icnnm_poll.restype = C.c_int32
+    lib.icnnm_set_profiling.argtypes = [P, C.c_int32]
+    lib.icnnm_set_profiling.restype = C.c_int32
+    lib.icnnm_stage_times.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
+    lib.icnnm_stage_times.restype = C.c_int32
     return lib
 
 
@@ -232,6 +238,20 @@ class Library:
         if rc != OK:
             self._raise(rc)
         return int(t.value)
+
+    def set_profiling(self, on: bool):
+        rc = self.lib.icnnm_set_profiling(self.ctx, int(bool(on)))
+        if rc != OK:
+            self._raise(rc)
+
+    def stage_times(self, reset=True):
+        """{stage: (total_ms, launches)} accumulated while profiling was on."""
+        ms = (C.c_double * 4)()
+        n = (C.c_int64 * 4)()
+        rc = self.lib.icnnm_stage_times(self.ctx, ms, n, int(bool(reset)))
+        if rc != OK:
+            self._raise(rc)
+        return {name: (ms[i], int(n[i])) for i, name in enumerate(STAGES)}
 
     def poll(self, ticket):
         """Returns (status, info dict); status PENDING while the request runs."""

@@ -60,6 +60,9 @@ def main():
     ap.add_argument("--cpu-sample-iters", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--iters", type=int, default=0, help="override the iteration count (short profiler runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -70,6 +73,8 @@ def main():
     from paper_2604_17001_amd import icnnm
 
     wl = _workload(args.workload)
+    if args.iters > 0:
+        wl.iters = args.iters
     prob = wl.problems[0]
     kd = wl.kdims
     m, k = prob.m, prob.k
@@ -99,8 +104,8 @@ def main():
     rel_err = None
     gV = os.path.join(ROOT, "tests", "golden", f"{args.workload}_V.npy")
     gL = os.path.join(ROOT, "tests", "golden", f"{args.workload}_L.npy")
-    if os.path.exists(gV) and os.path.exists(gL):
-        Vg = torch.from_numpy(np.load(gV)).to(dev)
+    if os.path.exists(gV) and os.path.exists(gL) and args.iters == 0:
+        Vg = torch.from_numpy(np.ascontiguousarray(np.load(gV))).to(dev)
         Lg, _ = lib.solve(M, mask, Vg, kd, **kw)
         ref = np.load(gL)
         rel_err = float(np.linalg.norm(Lg.cpu().numpy().astype(np.float64) - ref) / np.linalg.norm(ref))
@@ -124,6 +129,13 @@ def main():
         roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                     "flops_per_launch": flops}
+
+    if args.calibrate_copy:
+        x = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
 
     cpu = None
     if not args.no_cpu_baseline:

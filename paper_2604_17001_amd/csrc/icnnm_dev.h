@@ -23,6 +23,7 @@ constexpr int kThreads = 256;  // 4 wavefronts of 64 lanes
 constexpr int kRowUnit = 64;   // spatial rows per wave work unit (two 32-row MFMA groups)
 constexpr int kColUnit = 64;   // columns per wave work unit (two 32-column MFMA blocks)
 constexpr int kGroup = 256;    // columns (forward) or kernel offsets (adjoint) per workgroup
+constexpr int kLStepElems = 64; // output elements per L-step workgroup (four lanes each)
 
 enum Phase : int32_t { kNew = 0, kInit = 1, kRun = 2, kDone = 3 };
 

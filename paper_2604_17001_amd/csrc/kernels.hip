@@ -19,7 +19,26 @@
 
 namespace icnnm {
 
+constexpr int kLanesPerElem = kThreads / kLStepElems;      // L-step lanes per output element
+
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// Pointers read from descriptors are generic; loads through them become flat
+// loads, which the wait-count logic tracks conservatively. These casts let the
+// compiler emit global loads and keep prefetches in flight.
+// (The host pass only parses kernel bodies, so it sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef __attribute__((address_space(1))) const float4 gcfloat4;
+typedef __attribute__((address_space(1))) float4 gfloat4;
+typedef __attribute__((address_space(1))) const float gcfloat;
+#else
+typedef const float4 gcfloat4;
+typedef float4 gfloat4;
+typedef const float gcfloat;
+#endif
+__device__ __forceinline__ gcfloat4* gc4(const void* p) { return (gcfloat4*)(p); }
+__device__ __forceinline__ gfloat4* g4(void* p) { return (gfloat4*)(p); }
+__device__ __forceinline__ gcfloat* gc1(const void* p) { return (gcfloat*)(p); }
 
 __device__ __forceinline__ int wrapi(int v, int m) {
   v %= m;
@@ -115,7 +134,7 @@ __device__ __forceinline__ void tile_origin(int lt, const InstDev& I, int* o) {
 // and per-tile partial sums of Q^2, W^2 (per column) and (Z - W)^2.
 // grid = (tiles, kp / 256 column groups); each wave takes (64 rows x 64 columns) units.
 // =====================================================================================
-__global__ __launch_bounds__(kThreads) void k_forward(StageArgs a) {
+__global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   extern __shared__ float smem[];
   const int2 tt = a.tiles[blockIdx.x];
   const InstDev& I = a.inst[tt.x];
@@ -132,9 +151,11 @@ __global__ __launch_bounds__(kThreads) void k_forward(StageArgs a) {
   tile_origin(lt, I, o);
   const int E123 = I.E123;
   float* halo = smem;                                   // E123
-  int* offs = reinterpret_cast<int*>(halo + E123);      // kp
+  // kernel-offset table by half-step: offs2[h*16 + half*8 + jj] = off(s) for
+  // s = (h/2)*32 + (h%2)*16 + 2*jj + half (16-byte aligned rows)
+  int* offs2 = reinterpret_cast<int*>(smem + ((E123 + 3) & ~3));
   const int nrc = I.bm / kRowUnit, ncc = CG / kColUnit;
-  float* colq = reinterpret_cast<float*>(offs + kp);    // [nrc][CG]
+  float* colq = reinterpret_cast<float*>(offs2 + kp);   // [nrc][CG]
   float* colw = colq + nrc * CG;                        // [nrc][CG]
   float* rred = colw + nrc * CG;                        // [nrc * ncc]
 
@@ -149,11 +170,15 @@ __global__ __launch_bounds__(kThreads) void k_forward(StageArgs a) {
     int g2 = wrapi(o[2] - (I.k[2] - 1) + x2, I.m[2]);
     halo[x] = L[((int64_t)g0 * I.m[1] + g1) * I.m[2] + g2];
   }
-  for (int s = tid; s < kp; s += kThreads) offs[s] = kernel_off(s, I, k);
+  for (int e = tid; e < kp; e += kThreads) {
+    const int h = e >> 4, hf = (e >> 3) & 1, jj = e & 7;
+    offs2[e] = kernel_off((h >> 1) * 32 + (h & 1) * 16 + 2 * jj + hf, I, k);
+  }
   __syncthreads();
 
   const float ratio = (float)I.st->ratio;
   const int nkb = kp / 32;
+  const int nhs = 2 * nkb;  // half-steps of 8 MFMA k-steps (16 kernel offsets)
   for (int u = wave; u < nrc * ncc; u += 4) {
     const int rc = u / ncc, cc = u % ncc;
     const int c0 = cg * CG + cc * kColUnit;
@@ -168,68 +193,102 @@ __global__ __launch_bounds__(kThreads) void k_forward(StageArgs a) {
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = (floatx16)(0.0f);
 
-    const float* vf0 = a.Vf + ((size_t)(c0 / 32) * nkb) * 1024 + lane * 16;
-    const float* vf1 = vf0 + (size_t)nkb * 1024;
-    for (int sb = 0; sb < nkb; ++sb) {
-      float av0[16], av1[16];
-      load16(vf0 + (size_t)sb * 1024, av0);
-      load16(vf1 + (size_t)sb * 1024, av1);
+    // V fragments: per (column block, offset block) 16 floats per lane in k-step
+    // order, consumed in halves of 8 k-steps. Each iteration first takes the
+    // operands loaded during the previous one, then issues the loads of the next
+    // half-step, then runs its 32 MFMAs, so the loads overlap the MFMAs.
+    gcfloat4* vf0 = gc4(a.Vf) + (size_t)(c0 / 32) * nkb * 256 + lane * 4;
+    gcfloat4* vf1 = vf0 + (size_t)nkb * 256;
+    float4 vn[2][2];
+    float bn[2][8];
+    auto load_half = [&](int h) {
+      const size_t q = (size_t)(h >> 1) * 256 + (h & 1) * 2;
+      vn[0][0] = vf0[q];
+      vn[0][1] = vf0[q + 1];
+      vn[1][0] = vf1[q];
+      vn[1][1] = vf1[q + 1];
+      const int4* ot = reinterpret_cast<const int4*>(offs2 + h * 16 + half * 8);
+      const int4 oa = ot[0], ob = ot[1];
+      const int ov[8] = {oa.x, oa.y, oa.z, oa.w, ob.x, ob.y, ob.z, ob.w};
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int off = offs[sb * 32 + 2 * j + half];
-        const float b0 = halo[base[0] - off];
-        const float b1 = halo[base[1] - off];
-        acc[0][0] = mfma32(av0[j], b0, acc[0][0]);
-        acc[0][1] = mfma32(av0[j], b1, acc[0][1]);
-        acc[1][0] = mfma32(av1[j], b0, acc[1][0]);
-        acc[1][1] = mfma32(av1[j], b1, acc[1][1]);
+      for (int jj = 0; jj < 8; ++jj) {
+        bn[0][jj] = halo[base[0] - ov[jj]];
+        bn[1][jj] = halo[base[1] - ov[jj]];
+      }
+    };
+    load_half(0);
+    for (int h = 0; h < nhs; ++h) {
+      const float a0[8] = {vn[0][0].x, vn[0][0].y, vn[0][0].z, vn[0][0].w,
+                           vn[0][1].x, vn[0][1].y, vn[0][1].z, vn[0][1].w};
+      const float a1[8] = {vn[1][0].x, vn[1][0].y, vn[1][0].z, vn[1][0].w,
+                           vn[1][1].x, vn[1][1].y, vn[1][1].z, vn[1][1].w};
+      float b0[8], b1[8];
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        b0[jj] = bn[0][jj];
+        b1[jj] = bn[1][jj];
+      }
+      if (h + 1 < nhs) load_half(h + 1);
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        acc[0][0] = mfma32(a0[jj], b0[jj], acc[0][0]);
+        acc[0][1] = mfma32(a0[jj], b1[jj], acc[0][1]);
+        acc[1][0] = mfma32(a1[jj], b0[jj], acc[1][0]);
+        acc[1][1] = mfma32(a1[jj], b1[jj], acc[1][1]);
       }
     }
 
-    // fused epilogue
+    // fused epilogue, four columns at a time
     float rsum = 0.f;
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
       const int cblk = c0 / 32 + cb;
-      float sv[16];
-      if (!init) load_cols16(I.s, cblk * 32, half, sv);
       float qs[16], ws[16];
 #pragma unroll
       for (int v = 0; v < 16; ++v) qs[v] = ws[v] = 0.f;
 #pragma unroll
       for (int ib = 0; ib < 2; ++ib) {
-        const size_t sidx = ((((size_t)lt * (I.bm / 32) + rc * 2 + ib) * nkb + cblk) * 64 + lane) * 16;
-        float uo[16], qo[16], un[16], qn[16];
-        if (!init) {
-          load16(I.U + sidx, uo);
-          load16(I.Q + sidx, qo);
-        }
+        const size_t sidx = ((((size_t)lt * (I.bm / 32) + rc * 2 + ib) * nkb + cblk) * 64 + lane) * 4;
+        float4* Up = reinterpret_cast<float4*>(I.U) + sidx;
+        float4* Qp = reinterpret_cast<float4*>(I.Q) + sidx;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          float w = acc[cb][ib][v];
-          float unew, qnew;
-          if (!valid[ib]) {
-            w = 0.f;
-            unew = 0.f;
-            qnew = 0.f;
-          } else if (init) {
-            unew = 0.f;
-            qnew = w;
-          } else {
-            const float z = sv[v] * qo[v];
-            const float g = uo[v] + z;
-            unew = (g - w) * ratio;
-            qnew = w - unew;
-            const float d = z - w;
-            rsum += d * d;
+        for (int g = 0; g < 4; ++g) {
+          float4 u4 = make_float4(0.f, 0.f, 0.f, 0.f), q4 = u4, s4 = u4;
+          if (!init) {
+            u4 = Up[g];
+            q4 = Qp[g];
+            s4 = *reinterpret_cast<const float4*>(I.s + cblk * 32 + g * 8 + half * 4);
           }
-          un[v] = unew;
-          qn[v] = qnew;
-          qs[v] += qnew * qnew;
-          ws[v] += w * w;
+          const float uo[4] = {u4.x, u4.y, u4.z, u4.w}, qo[4] = {q4.x, q4.y, q4.z, q4.w};
+          const float sv[4] = {s4.x, s4.y, s4.z, s4.w};
+          float un[4], qn[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            float w = acc[cb][ib][4 * g + e];
+            float unew, qnew;
+            if (!valid[ib]) {
+              w = 0.f;
+              unew = 0.f;
+              qnew = 0.f;
+            } else if (init) {
+              unew = 0.f;
+              qnew = w;
+            } else {
+              const float z = sv[e] * qo[e];
+              const float gg = uo[e] + z;
+              unew = (gg - w) * ratio;
+              qnew = w - unew;
+              const float d = z - w;
+              rsum += d * d;
+            }
+            un[e] = unew;
+            qn[e] = qnew;
+            qs[4 * g + e] += qnew * qnew;
+            ws[4 * g + e] += w * w;
+          }
+          Up[g] = make_float4(un[0], un[1], un[2], un[3]);
+          Qp[g] = make_float4(qn[0], qn[1], qn[2], qn[3]);
         }
-        store16(I.U + sidx, un);
-        store16(I.Q + sidx, qn);
       }
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
@@ -252,8 +311,8 @@ __global__ __launch_bounds__(kThreads) void k_forward(StageArgs a) {
       q += colq[rc * CG + c];
       w += colw[rc * CG + c];
     }
-    I.qpart[(size_t)lt * kp + cg * CG + c] = q;
-    I.wpart[(size_t)lt * kp + cg * CG + c] = w;
+    I.qpart[(size_t)(cg * CG + c) * I.ntiles + lt] = q;
+    I.wpart[(size_t)(cg * CG + c) * I.ntiles + lt] = w;
   }
   if (tid == 0) {
     float r = 0.f;
@@ -264,11 +323,16 @@ __global__ __launch_bounds__(kThreads) void k_forward(StageArgs a) {
 
 // =====================================================================================
 // adjoint: T_partial = col2im(H), H = G V^T with G = U + s.Q (= (Y + theta Z)/theta).
-// grid = (tiles, kp / 256 offset groups). Each wave computes H^T for (64 offsets x 64
-// rows) units over the whole reduction over eigendirections, then scatters
-// H[j, s] onto box position base(j) - off(s) with LDS float atomics.
+// grid = (tiles, kp / 256 offset groups). The units of a workgroup (64 rows x 64
+// offsets each, one per wavefront) are processed in rounds of four: each wavefront
+// runs its unit's contraction on MFMA over all eigendirections and stores H^T in
+// LDS; then every thread gathers, for the box positions it owns, the H entries that
+// land on them (t = j - s), in a fixed order. No atomics: the result is
+// deterministic and independent of how the work was scheduled.
 // =====================================================================================
-__global__ __launch_bounds__(kThreads) void k_adjoint(StageArgs a) {
+constexpr int kMaxOwned = 16;  // box positions per thread (E123 <= 4096)
+
+__global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
   extern __shared__ float smem[];
   const int2 tt = a.tiles[blockIdx.x];
   const InstDev& I = a.inst[tt.x];
@@ -278,68 +342,133 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(StageArgs a) {
   const int SGW = kp < kGroup ? kp : kGroup;
   const int lt = tt.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5;
-  int o[3];
-  tile_origin(lt, I, o);
-  const int E123 = I.E123;
-  float* box = smem;
-  int* offs = reinterpret_cast<int*>(box + E123);
-  for (int x = tid; x < E123; x += kThreads) box[x] = 0.f;
-  for (int s = tid; s < kp; s += kThreads) offs[s] = kernel_off(s, I, k);
-  __syncthreads();
+  const int bm = I.bm;
+  const int nrc = bm / kRowUnit, nsc = SGW / kColUnit;
+  const int units = nrc * nsc;
+  const int rounds = units >= 4 ? units / 4 : 1;  // four units per round (fewer when small)
+  const int spr = (SGW / rounds);             // kernel offsets per round
+  const int hstride = bm + 4;                 // LDS row stride of the staged H^T
+  float* Hs = smem;                           // [spr][hstride]
 
-  const int nrc = I.bm / kRowUnit, nsc = SGW / kColUnit;
+  // owned box positions and their valid kernel-offset ranges per dimension
+  const int E123 = I.E123;
+  const int k0 = I.k[0], k1 = I.k[1], k2 = I.k[2], k12 = k1 * k2;
+  float tacc[kMaxOwned];
+#pragma unroll
+  for (int i = 0; i < kMaxOwned; ++i) tacc[i] = 0.f;
+
   const int nkb = kp / 32;
-  for (int u = wave; u < nrc * nsc; u += 4) {
-    const int rc = u / nsc, sc = u % nsc;
+  const int nhb = 2 * nkb;  // half column blocks of 8 MFMA k-steps
+  gcfloat4* U4 = gc4(I.U);
+  gcfloat4* Q4 = gc4(I.Q);
+  const float* S = I.s;
+  for (int rd = 0; rd < rounds; ++rd) {
+    const int u = rd * 4 + wave;
+    const int rc = u % nrc, sc = u / nrc;    // a round covers whole offset chunks
     const int s0 = sg * SGW + sc * kColUnit;
+    const int S0 = sg * SGW + rd * spr;      // first offset staged this round
+    if (u < units) {
     floatx16 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = (floatx16)(0.0f);
-    const float* va0 = a.Va + ((size_t)(s0 / 32) * nkb) * 1024 + lane * 16;
-    const float* va1 = va0 + (size_t)nkb * 1024;
-    for (int cb = 0; cb < nkb; ++cb) {
-      float sv[16];
-      load_cols16(I.s, cb * 32, half, sv);
-      float g[2][16];
+    gcfloat4* va0 = gc4(a.Va) + (size_t)(s0 / 32) * nkb * 256 + lane * 4;
+    gcfloat4* va1 = va0 + (size_t)nkb * 256;
+    const size_t row0 = ((size_t)lt * (bm / 32) + rc * 2) * nkb;  // row group jb: (row0 + jb * nkb + cb)
+    // operands of half block h (column block cb = h/2, part p = h%2); each iteration
+    // consumes the loads of the previous one before issuing its own
+    float4 fu[2][2], fq[2][2], fs[2], fv[2][2];
+    auto load = [&](int h) {
+      const int cb = h >> 1, p = h & 1;
 #pragma unroll
       for (int jb = 0; jb < 2; ++jb) {
-        const size_t sidx = ((((size_t)lt * (I.bm / 32) + rc * 2 + jb) * nkb + cb) * 64 + lane) * 16;
-        float uo[16], qo[16];
-        load16(I.U + sidx, uo);
-        load16(I.Q + sidx, qo);
-#pragma unroll
-        for (int v = 0; v < 16; ++v) g[jb][v] = uo[v] + sv[v] * qo[v];
+        const size_t o = (row0 + (size_t)jb * nkb + cb) * 256 + lane * 4 + 2 * p;
+        fu[jb][0] = U4[o];
+        fu[jb][1] = U4[o + 1];
+        fq[jb][0] = Q4[o];
+        fq[jb][1] = Q4[o + 1];
       }
-      float va[2][16];
-      load16(va0 + (size_t)cb * 1024, va[0]);
-      load16(va1 + (size_t)cb * 1024, va[1]);
+      fs[0] = *gc4(S + cb * 32 + (2 * p) * 8 + half * 4);
+      fs[1] = *gc4(S + cb * 32 + (2 * p + 1) * 8 + half * 4);
+      const size_t ov = (size_t)cb * 256 + 2 * p;
+      fv[0][0] = va0[ov];
+      fv[0][1] = va0[ov + 1];
+      fv[1][0] = va1[ov];
+      fv[1][1] = va1[ov + 1];
+    };
+    load(0);
+    for (int h = 0; h < nhb; ++h) {
+      float g[2][8];
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        acc[0][0] = mfma32(va[0][v], g[0][v], acc[0][0]);
-        acc[0][1] = mfma32(va[0][v], g[1][v], acc[0][1]);
-        acc[1][0] = mfma32(va[1][v], g[0][v], acc[1][0]);
-        acc[1][1] = mfma32(va[1][v], g[1][v], acc[1][1]);
-      }
-    }
+      for (int jb = 0; jb < 2; ++jb) {
 #pragma unroll
-    for (int jb = 0; jb < 2; ++jb) {
-      bool valid;
-      const int base = row_base(rc * 64 + jb * 32 + (lane & 31), I, o, valid);
-#pragma unroll
-      for (int sb = 0; sb < 2; ++sb) {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int s = s0 + sb * 32 + acc_col(v, half);
-          if (s < k) atomicAdd(&box[base - offs[s]], acc[sb][jb][v]);
+        for (int t = 0; t < 2; ++t) {
+          g[jb][4 * t + 0] = fu[jb][t].x + fs[t].x * fq[jb][t].x;
+          g[jb][4 * t + 1] = fu[jb][t].y + fs[t].y * fq[jb][t].y;
+          g[jb][4 * t + 2] = fu[jb][t].z + fs[t].z * fq[jb][t].z;
+          g[jb][4 * t + 3] = fu[jb][t].w + fs[t].w * fq[jb][t].w;
         }
       }
+      const float v0[8] = {fv[0][0].x, fv[0][0].y, fv[0][0].z, fv[0][0].w,
+                           fv[0][1].x, fv[0][1].y, fv[0][1].z, fv[0][1].w};
+      const float v1[8] = {fv[1][0].x, fv[1][0].y, fv[1][0].z, fv[1][0].w,
+                           fv[1][1].x, fv[1][1].y, fv[1][1].z, fv[1][1].w};
+      if (h + 1 < nhb) load(h + 1);
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        acc[0][0] = mfma32(v0[jj], g[0][jj], acc[0][0]);
+        acc[0][1] = mfma32(v0[jj], g[1][jj], acc[0][1]);
+        acc[1][0] = mfma32(v1[jj], g[0][jj], acc[1][0]);
+        acc[1][1] = mfma32(v1[jj], g[1][jj], acc[1][1]);
+      }
     }
+    // stage H^T of this unit: Hs[s - S0][row]
+#pragma unroll
+    for (int sb = 0; sb < 2; ++sb)
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int sl = s0 + sb * 32 + acc_col(v, half) - S0;
+          Hs[sl * hstride + rc * 64 + jb * 32 + (lane & 31)] = acc[sb][jb][v];
+        }
+    }
+    __syncthreads();
+    // gather: box position t' (box coordinates) receives H[j = t' - (k-1) + s][s]
+    // for the kernel offsets s of this round with j inside the tile
+    const int S1 = min(S0 + spr, k);
+#pragma unroll
+    for (int i = 0; i < kMaxOwned; ++i) {
+      const int x = tid + i * kThreads;
+      if (x >= E123) break;
+      const int x0 = x / (I.E[1] * I.E[2]), rem = x - x0 * (I.E[1] * I.E[2]);
+      const int x1 = rem / I.E[2], x2 = rem - x1 * I.E[2];
+      // s_d in [lo_d, hi_d) keeps j_d = x_d - (k_d - 1) + s_d inside [0, b_d)
+      const int lo0 = max(0, k0 - 1 - x0), hi0 = min(k0, k0 - 1 - x0 + I.b[0]);
+      const int lo1 = max(0, k1 - 1 - x1), hi1 = min(k1, k1 - 1 - x1 + I.b[1]);
+      const int lo2 = max(0, k2 - 1 - x2), hi2 = min(k2, k2 - 1 - x2 + I.b[2]);
+      float sum = tacc[i];
+      for (int p = max(lo0, S0 / k12); p < hi0 && p * k12 < S1; ++p) {
+        const int j0 = x0 - (k0 - 1) + p;
+        for (int q = lo1; q < hi1; ++q) {
+          const int spq = (p * k1 + q) * k2;
+          const int r0 = max(lo2, S0 - spq), r1 = min(hi2, S1 - spq);
+          const int jrow = (j0 * I.b[1] + (x1 - (k1 - 1) + q)) * I.b[2] + (x2 - (k2 - 1));
+          for (int r = r0; r < r1; ++r) sum += Hs[(spq + r - S0) * hstride + jrow + r];
+        }
+      }
+      tacc[i] = sum;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   float* dst = I.part + ((size_t)lt * a.nsg + sg) * E123;
-  for (int x = tid; x < E123; x += kThreads) dst[x] = box[x];
+#pragma unroll
+  for (int i = 0; i < kMaxOwned; ++i) {
+    const int x = tid + i * kThreads;
+    if (x >= E123) break;
+    dst[x] = tacc[i];
+  }
 }
 
 // =====================================================================================
@@ -354,9 +483,43 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
   const InstDev& I = a.inst[lb.x];
   const int phase = I.st->phase;
   if (phase != kInit && phase != kRun) return;
-  const int64_t t = (int64_t)lb.y * kThreads + threadIdx.x;
+  // kLanesPerElem lanes share one output element; each sums every kLanesPerElem-th
+  // covering partial in a fixed order and the lanes combine by shuffles
+  const int sub = threadIdx.x & (kLanesPerElem - 1);
+  const int64_t t = (int64_t)lb.y * kLStepElems + (threadIdx.x / kLanesPerElem);
   double acc = 0.0;
-  if (t < I.mtot) {
+  const bool in = t < I.mtot;
+  float T = 0.f;
+  int t0 = 0, t1 = 0, t2 = 0;
+  if (in) {
+    t2 = (int)(t % I.m[2]);
+    const int64_t r = t / I.m[2];
+    t1 = (int)(r % I.m[1]);
+    t0 = (int)(r / I.m[1]);
+  }
+  if (in && phase == kRun) {
+    const int32_t* g0 = I.gtab + I.goff[0] + t0 * I.C[0];
+    const int32_t* g1 = I.gtab + I.goff[1] + t1 * I.C[1];
+    const int32_t* g2 = I.gtab + I.goff[2] + t2 * I.C[2];
+    const int nsg = a.nsg;
+    const int C12 = I.C[1] * I.C[2];
+    const int total = I.C[0] * C12 * nsg;
+    for (int idx = sub; idx < total; idx += kLanesPerElem) {
+      const int g = idx % nsg;
+      const int c = idx / nsg;
+      const int c2 = c % I.C[2];
+      const int c1 = (c / I.C[2]) % I.C[1];
+      const int c0 = c / C12;
+      const int e0 = g0[c0], e1 = g1[c1], e2 = g2[c2];
+      if ((e0 | e1 | e2) < 0) continue;
+      const int tile = ((e0 >> 16) * I.nt[1] + (e1 >> 16)) * I.nt[2] + (e2 >> 16);
+      const int pos = ((e0 & 0xffff) * I.E[1] + (e1 & 0xffff)) * I.E[2] + (e2 & 0xffff);
+      T += I.part[((size_t)tile * nsg + g) * I.E123 + pos];
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < kLanesPerElem; o <<= 1) T += __shfl_xor(T, o, 64);
+  if (in && sub == 0) {
     const bool obs = I.mask[t] != 0;
     const float mv = I.M[t];
     if (phase == kInit) {
@@ -364,31 +527,6 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
       I.L[t] = lv;
       acc = (double)lv * (double)lv;
     } else {
-      const int t2 = (int)(t % I.m[2]);
-      const int64_t r = t / I.m[2];
-      const int t1 = (int)(r % I.m[1]);
-      const int t0 = (int)(r / I.m[1]);
-      const int32_t* g0 = I.gtab + I.goff[0] + t0 * I.C[0];
-      const int32_t* g1 = I.gtab + I.goff[1] + t1 * I.C[1];
-      const int32_t* g2 = I.gtab + I.goff[2] + t2 * I.C[2];
-      const int nsg = a.nsg;
-      float T = 0.f;
-      for (int c0 = 0; c0 < I.C[0]; ++c0) {
-        const int e0 = g0[c0];
-        if (e0 < 0) break;
-        for (int c1 = 0; c1 < I.C[1]; ++c1) {
-          const int e1 = g1[c1];
-          if (e1 < 0) break;
-          for (int c2 = 0; c2 < I.C[2]; ++c2) {
-            const int e2 = g2[c2];
-            if (e2 < 0) break;
-            const int tile = ((e0 >> 16) * I.nt[1] + (e1 >> 16)) * I.nt[2] + (e2 >> 16);
-            const int pos = ((e0 & 0xffff) * I.E[1] + (e1 & 0xffff)) * I.E[2] + (e2 & 0xffff);
-            const float* p = I.part + (size_t)tile * nsg * I.E123 + pos;
-            for (int g = 0; g < nsg; ++g) T += p[(size_t)g * I.E123];
-          }
-        }
-      }
       const float tk = T / (float)a.k;
       float lv;
       if (!obs) {
@@ -415,16 +553,17 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
 }
 
 // =====================================================================================
-// colnorm: FP64 reduction of the per-tile partials in slices, the last arriving block
-// of an instance finishes: column norms -> shrink factors, penalty schedule,
-// residuals of the previous iteration, stopping decision.
+// colnorm: FP64 reduction of the per-tile partials. Block b of an instance reduces
+// columns 4b..4b+3 (one wavefront per column, lanes over tiles, fixed shuffle tree)
+// and a share of the scalar partials; the last arriving block finishes: column norms
+// -> shrink factors, penalty schedule, residuals of the previous iteration, stopping.
 // =====================================================================================
 __global__ __launch_bounds__(kThreads) void k_colnorm(StageArgs a) {
   const int2 sl = a.slices[blockIdx.x];
   const InstDev& I = a.inst[sl.x];
   InstState* st = I.st;
   const int phase = st->phase;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (phase == kDone) return;
   // a new instance only moves to initialisation; the move is made by the last
   // arriving block so that no block of this launch sees the new phase
@@ -439,39 +578,50 @@ __global__ __launch_bounds__(kThreads) void k_colnorm(StageArgs a) {
     return;
   }
   const int kp = a.kp;
-  const int stride = 2 * kp + 2;
-  double* out = I.slice + (size_t)sl.y * stride;
-  const int tb = sl.y * a.tiles_per_slice;
-  const int te = min(I.ntiles, tb + a.tiles_per_slice);
-  for (int c = tid; c < kp; c += kThreads) {
+  const int nt = I.ntiles;
+  double* colsum = I.slice;              // [kp][2]: sum Q^2, sum W^2
+  double* scal = I.slice + 2 * kp;       // [nslice][2]: (Z - W)^2, L-step sums
+  {
+    const int c = sl.y * 4 + wave;
+    const float* qp = I.qpart + (size_t)c * nt;
+    const float* wp = I.wpart + (size_t)c * nt;
     double q = 0.0, w = 0.0;
-    for (int tI = tb; tI < te; ++tI) {
-      q += (double)I.qpart[(size_t)tI * kp + c];
-      w += (double)I.wpart[(size_t)tI * kp + c];
+#pragma unroll 4
+    for (int t = lane; t < nt; t += 64) {
+      q += (double)qp[t];
+      w += (double)wp[t];
     }
-    out[c] = q;
-    out[kp + c] = w;
-  }
-  // scalars: (Z - W)^2 over the slice's tiles and this slice's share of L-step blocks
-  __shared__ double red[2][kThreads / 64];
-  double r = 0.0, dl = 0.0;
-  for (int i = tb * a.ncg + tid; i < te * a.ncg; i += kThreads) r += (double)I.rpart[i];
-  const int lpb = (I.nlblk + I.nslice - 1) / I.nslice;
-  const int lb0 = sl.y * lpb, lb1 = min(I.nlblk, lb0 + lpb);
-  for (int i = lb0 + tid; i < lb1; i += kThreads) dl += I.dlpart[i];
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    r += __shfl_xor(r, o, 64);
-    dl += __shfl_xor(dl, o, 64);
+    for (int o = 1; o < 64; o <<= 1) {
+      q += __shfl_xor(q, o, 64);
+      w += __shfl_xor(w, o, 64);
+    }
+    if (lane == 0) {
+      colsum[2 * c] = q;
+      colsum[2 * c + 1] = w;
+    }
   }
-  if ((tid & 63) == 0) {
-    red[0][tid >> 6] = r;
-    red[1][tid >> 6] = dl;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    out[2 * kp] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    out[2 * kp + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  {
+    __shared__ double red[2][kThreads / 64];
+    const int nr = nt * a.ncg;
+    const int rch = (nr + I.nslice - 1) / I.nslice, lch = (I.nlblk + I.nslice - 1) / I.nslice;
+    double r = 0.0, dl = 0.0;
+    for (int i = sl.y * rch + tid; i < min(nr, (sl.y + 1) * rch); i += kThreads) r += (double)I.rpart[i];
+    for (int i = sl.y * lch + tid; i < min(I.nlblk, (sl.y + 1) * lch); i += kThreads) dl += I.dlpart[i];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      r += __shfl_xor(r, o, 64);
+      dl += __shfl_xor(dl, o, 64);
+    }
+    if (lane == 0) {
+      red[0][wave] = r;
+      red[1][wave] = dl;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      scal[2 * sl.y] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+      scal[2 * sl.y + 1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+    }
   }
   // last-arriving block of this instance finishes
   __shared__ int last;
@@ -488,29 +638,23 @@ __global__ __launch_bounds__(kThreads) void k_colnorm(StageArgs a) {
   __shared__ double sh_obj[kThreads / 64], sh_max[kThreads / 64], sh_sc[2];
   double obj = 0.0, mx = 0.0;
   for (int c = tid; c < kp; c += kThreads) {
-    double w = 0.0, q = 0.0;
-    for (int j = 0; j < I.nslice; ++j) {
-      q += I.slice[(size_t)j * stride + c];
-      w += I.slice[(size_t)j * stride + kp + c];
-    }
-    obj += sqrt(w);
-    mx = fmax(mx, sqrt(q));
-    I.slice[c] = q;  // slice 0 row now holds the column sums (read back below by the same thread)
+    obj += sqrt(colsum[2 * c + 1]);
+    mx = fmax(mx, sqrt(colsum[2 * c]));
   }
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     obj += __shfl_xor(obj, o, 64);
     mx = fmax(mx, __shfl_xor(mx, o, 64));
   }
-  if ((tid & 63) == 0) {
-    sh_obj[tid >> 6] = obj;
-    sh_max[tid >> 6] = mx;
+  if (lane == 0) {
+    sh_obj[wave] = obj;
+    sh_max[wave] = mx;
   }
   if (tid == 0) {
     double rs = 0.0, ds = 0.0;
     for (int j = 0; j < I.nslice; ++j) {
-      rs += I.slice[(size_t)j * stride + 2 * kp];
-      ds += I.slice[(size_t)j * stride + 2 * kp + 1];
+      rs += scal[2 * j];
+      ds += scal[2 * j + 1];
     }
     sh_sc[0] = rs;
     sh_sc[1] = ds;
@@ -519,7 +663,7 @@ __global__ __launch_bounds__(kThreads) void k_colnorm(StageArgs a) {
   __shared__ int go_on;
   if (tid == 0) {
     st->counter = 0u;
-    const double objective = sh_obj[0] + sh_obj[1] + sh_obj[2] + sh_obj[3];
+    const double objective = ((sh_obj[0] + sh_obj[1]) + sh_obj[2]) + sh_obj[3];
     const double maxn = fmax(fmax(sh_max[0], sh_max[1]), fmax(sh_max[2], sh_max[3]));
     int go = 1;
     if (phase == kInit) {
@@ -567,7 +711,7 @@ __global__ __launch_bounds__(kThreads) void k_colnorm(StageArgs a) {
   if (!go_on) return;
   const double th = st->theta_cur;
   for (int c = tid; c < kp; c += kThreads) {
-    const double n = sqrt(I.slice[c]);
+    const double n = sqrt(colsum[2 * c]);
     const double sc = n > 0.0 ? fmax(0.0, 1.0 - 1.0 / (th * n)) : 0.0;
     I.s[c] = (float)sc;
   }

@@ -8,6 +8,8 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -112,20 +114,31 @@ static int pow2ceil(int v) {
 static int lds_forward_floats(const Plan& p, int kp) {
   const int CG = std::min(kp, kGroup);
   const int nrc = p.bm / kRowUnit, ncc = CG / kColUnit;
-  return p.E123 + kp + 2 * nrc * CG + nrc * ncc;
+  return ((p.E123 + 3) & ~3) + kp + 2 * nrc * CG + nrc * ncc;
 }
 
-static int lds_adjoint_floats(const Plan& p, int kp) { return p.E123 + kp; }
+static int lds_adjoint_floats(const Plan& p, int kp) {
+  // staged H^T of one round: (offsets per round) x (tile rows + 4)
+  const int SGW = std::min(kp, kGroup);
+  const int units = (p.bm / kRowUnit) * (SGW / kColUnit);
+  const int rounds = units >= 4 ? units / 4 : 1;
+  return (SGW / rounds) * (p.bm + 4);
+}
 
 static Plan make_plan(const int m[3], const int k[3], int kp) {
   Plan best{};
   double best_cost = 1e300;
   const int nsg = (kp + kGroup - 1) / kGroup;
+  // ICNNM_TILE=b0,b1,b2 forces one tile box (used to compare tile shapes)
+  int force[3] = {0, 0, 0};
+  if (const char* e = getenv("ICNNM_TILE")) sscanf(e, "%d,%d,%d", &force[0], &force[1], &force[2]);
   for (int bm : {64, 128, 256, 512}) {
-    for (int b2 = 1; b2 <= std::min(pow2ceil(m[2]), bm); b2 <<= 1) {
+    for (int b2 = 1; b2 <= bm; b2 <<= 1) {
+      if (b2 > pow2ceil(m[2]) && b2 * pow2ceil(m[1]) * pow2ceil(m[0]) > bm) continue;
       for (int b1 = 1; b1 * b2 <= bm && b1 <= pow2ceil(m[1]); b1 <<= 1) {
         const int b0 = bm / (b1 * b2);
         if (b0 * b1 * b2 != bm || b0 > pow2ceil(m[0])) continue;
+        if (force[0] > 0 && (b0 != force[0] || b1 != force[1] || b2 != force[2])) continue;
         Plan p{};
         for (int d = 0; d < 3; ++d) {
           p.m[d] = m[d];
@@ -144,13 +157,26 @@ static Plan make_plan(const int m[3], const int k[3], int kp) {
         p.E123 = p.E[0] * p.E[1] * p.E[2];
         p.ntiles = (int)ntiles;
         if (lds_forward_floats(p, kp) * 4 > 150 * 1024) continue;
+        {
+          if (bm / kRowUnit > 4 || p.E123 > 4096) continue;
+          if (lds_adjoint_floats(p, kp) * 4 > 80 * 1024) continue;
+        }
         if (p.E[0] > 65535 || p.E[1] > 65535 || p.E[2] > 65535 || ntiles > 65535 * 16) continue;
+        // cost model: rounds of resident workgroups (two per CU, limited by the
+        // adjoint's registers) x (units per wavefront + prologue/epilogue overhead),
+        // slowed when fewer than two wavefronts per SIMD are resident, times the
+        // padding of ragged tiles, the halo traffic and a preference for long
+        // innermost tile rows
         const double mt = (double)m[0] * m[1] * m[2];
         const double padded = (double)ntiles * bm / mt;
         const double halo = (double)p.E123 * nsg / (2.0 * bm * kp);
         const double wgs = (double)ntiles * nsg;
-        const double occ = wgs >= 2048 ? 1.0 : 1.0 + 0.5 * (2048 - wgs) / 2048;
-        const double cost = padded * (1.0 + halo) * occ;
+        const double slots = 256.0 * 2.0;
+        const double rounds = std::ceil(wgs / slots);
+        const double upw = (double)(bm / kRowUnit) * (std::min(kp, kGroup) / kColUnit) / 4.0;
+        const double eff = wgs >= slots ? 1.0 : 0.5 + 0.5 * wgs / slots;
+        const double inner = 1.0 + 0.005 * std::log2(32.0 / std::min(b2, 32));
+        const double cost = rounds * (std::max(upw, 1.0) + 0.5) / eff * padded * (1.0 + halo) * inner;
         if (cost < best_cost - 1e-12) {
           best_cost = cost;
           best = p;
@@ -161,8 +187,8 @@ static Plan make_plan(const int m[3], const int k[3], int kp) {
   if (best_cost >= 1e300) throw Error(ICNNM_E_INVALID, "no tile shape fits this problem");
   Plan& p = best;
   p.mtot = (int64_t)m[0] * m[1] * m[2];
-  p.nlblk = (int)((p.mtot + kThreads - 1) / kThreads);
-  p.nslice = (p.ntiles + kTilesPerSlice - 1) / kTilesPerSlice;
+  p.nlblk = (int)((p.mtot + kLStepElems - 1) / kLStepElems);
+  p.nslice = kp / 4;  // column-norm blocks: four columns (one wavefront each) per block
   // gather tables: for each coordinate t of dimension d, the (tile, box position) pairs
   // whose box position (n b - (k - 1) + p) mod m equals t
   int off = 0;
@@ -217,7 +243,7 @@ static size_t member_bytes(const Plan& p, int kp, int nsg, int ncg, int prec) {
   b += 2 * align256((size_t)p.ntiles * kp * 4);              // qpart, wpart
   b += align256((size_t)p.ntiles * ncg * 4);                 // rpart
   b += align256((size_t)p.nlblk * 8);                        // dlpart
-  b += align256((size_t)p.nslice * (2 * kp + 2) * 8);        // slice
+  b += align256((size_t)(2 * kp + 2 * p.nslice) * 8);          // column sums + scalar partials
   b += align256((size_t)kp * 4);                             // s
   b += align256(p.gtab.size() * 4);                          // gather tables
   if (prec != kFP32) b += 2 * align256((size_t)p.mtot * 4);  // Lprev, T
@@ -322,7 +348,7 @@ struct Group {
     d.wpart = (float*)take((size_t)p.ntiles * kp * 4);
     d.rpart = (float*)take((size_t)p.ntiles * ncg * 4);
     d.dlpart = (double*)take((size_t)p.nlblk * 8);
-    d.slice = (double*)take((size_t)p.nslice * (2 * kp + 2) * 8);
+    d.slice = (double*)take((size_t)(2 * kp + 2 * p.nslice) * 8);
     d.s = (float*)take((size_t)kp * 4);
     int32_t* gt = (int32_t*)take(p.gtab.size() * 4);
     d.gtab = gt;

@@ -28,6 +28,20 @@ sys.path.insert(0, ROOT)
 
 PEAKS = {"fp32_mfma": 157.3, "bf16_mfma": 2500.0, "fp16_mfma": 2500.0, "hbm_gbs": 8000.0}
 
+# HBM bytes per iterating launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by
+# the same counters on a plain 256 MiB copy (fetch x2.0, write x1.0); valid only for the
+# kernel source they were taken on (sha256 prefix of kernels.hip)
+TRAFFIC = {
+    ("c2", "fp32", "forward"): {"bytes": 308.3e6, "src": "8a13b48b84a425ac"},
+    ("c2", "fp32", "adjoint"): {"bytes": 274.2e6, "src": "8a13b48b84a425ac"},
+}
+
+
+def _kernel_src_hash():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2604_17001_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
 
 def _workload(name):
     from paper_2604_17001_amd import inputs
@@ -126,8 +140,10 @@ def main():
         flops = 2.0 * m * k * k          # one m x k x k contraction per launch
         achieved = flops / (stages[dom]["avg_us"] * 1e-6) / 1e12
         peak = PEAKS["fp32_mfma"] if args.precision == "fp32" else PEAKS[f"{args.precision}_mfma"]
+        tr = TRAFFIC.get((args.workload, args.precision, dom))
+        traffic = tr["bytes"] if tr and tr["src"] == _kernel_src_hash() and args.iters == 0 else None
         roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
-                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                     "flops_per_launch": flops}
 
     if args.calibrate_copy:

@@ -42,19 +42,20 @@ struct alignas(16) InstState {
   int32_t converged;
   int32_t status;     // 0 ok, -5 numeric
   uint32_t counter;   // arrival counter of the column-norm reduction (reset by the last block)
-  int32_t refresh;    // reduced precision: this iteration evaluates in FP32
+  int32_t refresh;    // reduced precision: this iteration evaluates both contractions in FP32
   int32_t pad[2];
+  double ratio_prev;  // ratio of the previous iteration (reconstructs the previous G)
 };
 
 struct alignas(16) InstDev {
   int32_t m[3], k[3], b[3], E[3], nt[3], C[3], goff[3];
-  int32_t ntiles, bm, E123, nlblk, nslice, lblk0, max_iter, refresh_every;
+  int32_t ntiles, bm, E123, nlblk, nslice, prec, max_iter, refresh_every;
   int64_t mtot;
   double lam, rho, theta_max, tol, theta0;
   const float* M;
   const uint8_t* mask;
   float* L;         // current iterate (C order)
-  float* Lprev;     // reduced precision: iterate at the last forward evaluation
+  float* D;         // reduced precision: L^t - L^{t-1}, the operand of the delta forward
   float* U;         // scaled dual Y / theta, tile layout
   float* Q;         // W - U, tile layout
   float* part;      // adjoint halo partials [ntiles][nsg][E123]
@@ -64,7 +65,7 @@ struct alignas(16) InstDev {
   double* dlpart;   // [nlblk] L-step partial sums
   double* slice;    // [nslice][2 kp + 2] FP64 slice sums of the norm reduction
   float* s;         // shrink factors [kp]
-  float* T;         // reduced precision: running A_k^*(G V^T) / k  [m]
+  float* T;         // reduced precision: running A_k^*(G V^T) / k, updated by deltas  [m]
   const int32_t* gtab;  // per-dimension gather tables, entries (tile << 16) | position, -1 = none
   InstState* st;
 };
@@ -85,9 +86,11 @@ struct StageArgs {
 
 // Launchers (defined in kernels.hip). All take the stream to launch on.
 void launch_colnorm(const StageArgs& a, int nslices_total, hipStream_t st);
-void launch_adjoint(const StageArgs& a, int ntiles_total, int lds_floats, hipStream_t st);
+// mode 0: FP32 contraction (initialisation, FP32 solves, refresh iterations);
+// mode 1 / 2: BF16 / FP16 contraction of the change since the previous iteration
+void launch_adjoint(const StageArgs& a, int ntiles_total, int lds_floats, int mode, hipStream_t st);
 void launch_lstep(const StageArgs& a, int nlblocks_total, hipStream_t st);
-void launch_forward(const StageArgs& a, int ntiles_total, int lds_floats, hipStream_t st);
+void launch_forward(const StageArgs& a, int ntiles_total, int lds_floats, int mode, hipStream_t st);
 void launch_prep_v(const float* V, int k, int kp, float* Vf, float* Va, void* Vf_lo,
                    void* Va_lo, int prec, hipStream_t st);
 void launch_check_v(const float* V, int k, float* out_maxdev, hipStream_t st);

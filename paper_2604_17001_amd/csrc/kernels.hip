@@ -23,6 +23,38 @@ constexpr int kLanesPerElem = kThreads / kLStepElems;      // L-step lanes per o
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
+// Reduced-precision MFMA: v_mfma_f32_32x32x16_{bf16,f16}. Lane l supplies the eight
+// consecutive K entries (l/32)*8 .. (l/32)*8+7 of row l%32 of A and of column l%32 of B;
+// the accumulator layout is that of the 32x32 FP32 MFMA.
+template <int MODE>
+struct LowP;
+template <>
+struct LowP<kBF16> {
+  typedef __bf16 h;
+  typedef __bf16 v8 __attribute__((ext_vector_type(8)));
+  typedef __bf16 v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ floatx16 mfma(v8 a, v8 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct LowP<kFP16> {
+  typedef _Float16 h;
+  typedef _Float16 v8 __attribute__((ext_vector_type(8)));
+  typedef _Float16 v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ floatx16 mfma(v8 a, v8 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+// Which contraction a stage kernel of mode MODE runs for an iterating instance:
+// FP32 on FP32 solves and on refresh iterations, the reduced precision otherwise.
+template <int MODE>
+__device__ __forceinline__ bool runs_iteration(const InstDev& I, const InstState* st) {
+  const bool full = (I.prec == kFP32) || st->refresh;
+  return MODE == kFP32 ? full : (!full && I.prec == MODE);
+}
+
 // Pointers read from descriptors are generic; loads through them become flat
 // loads, which the wait-count logic tracks conservatively. These casts let the
 // compiler emit global loads and keep prefetches in flight.
@@ -134,12 +166,17 @@ __device__ __forceinline__ void tile_origin(int lt, const InstDev& I, int* o) {
 // and per-tile partial sums of Q^2, W^2 (per column) and (Z - W)^2.
 // grid = (tiles, kp / 256 column groups); each wave takes (64 rows x 64 columns) units.
 // =====================================================================================
+template <int MODE>
 __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   extern __shared__ float smem[];
   const int2 tt = a.tiles[blockIdx.x];
   const InstDev& I = a.inst[tt.x];
   const int phase = I.st->phase;
-  if (phase != kInit && phase != kRun) return;
+  if (MODE == kFP32) {
+    if (phase != kInit && !(phase == kRun && runs_iteration<MODE>(I, I.st))) return;
+  } else {
+    if (!(phase == kRun && runs_iteration<MODE>(I, I.st))) return;
+  }
   const bool init = phase == kInit;
   const int kp = a.kp, k = a.k;
   const int cg = blockIdx.y;
@@ -150,35 +187,60 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   int o[3];
   tile_origin(lt, I, o);
   const int E123 = I.E123;
-  float* halo = smem;                                   // E123
-  // kernel-offset table by half-step: offs2[h*16 + half*8 + jj] = off(s) for
-  // s = (h/2)*32 + (h%2)*16 + 2*jj + half (16-byte aligned rows)
-  int* offs2 = reinterpret_cast<int*>(smem + ((E123 + 3) & ~3));
-  const int nrc = I.bm / kRowUnit, ncc = CG / kColUnit;
-  float* colq = reinterpret_cast<float*>(offs2 + kp);   // [nrc][CG]
-  float* colw = colq + nrc * CG;                        // [nrc][CG]
-  float* rred = colw + nrc * CG;                        // [nrc * ncc]
-
-  // halo of L over the tile box extended backwards by k - 1, with circular wrap
-  const float* L = I.L;
   const int E12 = I.E[1] * I.E[2];
-  for (int x = tid; x < E123; x += kThreads) {
-    int x0 = x / E12, rem = x - x0 * E12;
-    int x1 = rem / I.E[2], x2 = rem - x1 * I.E[2];
-    int g0 = wrapi(o[0] - (I.k[0] - 1) + x0, I.m[0]);
-    int g1 = wrapi(o[1] - (I.k[1] - 1) + x1, I.m[1]);
-    int g2 = wrapi(o[2] - (I.k[2] - 1) + x2, I.m[2]);
-    halo[x] = L[((int64_t)g0 * I.m[1] + g1) * I.m[2] + g2];
-  }
-  for (int e = tid; e < kp; e += kThreads) {
-    const int h = e >> 4, hf = (e >> 3) & 1, jj = e & 7;
-    offs2[e] = kernel_off((h >> 1) * 32 + (h & 1) * 16 + 2 * jj + hf, I, k);
+  const int nrc = I.bm / kRowUnit, ncc = CG / kColUnit;
+  // FP32: halo of L (E123 floats) + offset table offs2[h*16 + half*8 + jj] = off(s),
+  //       s = (h/2)*32 + (h%2)*16 + 2*jj + half
+  // reduced precision: halo of D = L^t - L^{t-1} expanded along the innermost
+  //       dimension, E4[y][d] = D_halo[y - d] (d < 4), so one 8-byte read yields four
+  //       consecutive kernel offsets; offset table offs4[kk*4 + half*2 + g] = off(s)
+  //       for s = 16*kk + 8*half + 4*g
+  const int halo_floats = MODE == kFP32 ? ((E123 + 3) & ~3) : 2 * E123;
+  float* halo = smem;
+  int* offs2 = reinterpret_cast<int*>(smem + halo_floats);
+  const int noffs = MODE == kFP32 ? kp : kp / 4;
+  float* colq = reinterpret_cast<float*>(offs2 + noffs);  // [nrc][CG]
+  float* colw = colq + nrc * CG;                          // [nrc][CG]
+  float* rred = colw + nrc * CG;                          // [nrc * ncc]
+
+  if constexpr (MODE == kFP32) {
+    // halo of L over the tile box extended backwards by k - 1, with circular wrap
+    const float* L = I.L;
+    for (int x = tid; x < E123; x += kThreads) {
+      int x0 = x / E12, rem = x - x0 * E12;
+      int x1 = rem / I.E[2], x2 = rem - x1 * I.E[2];
+      int g0 = wrapi(o[0] - (I.k[0] - 1) + x0, I.m[0]);
+      int g1 = wrapi(o[1] - (I.k[1] - 1) + x1, I.m[1]);
+      int g2 = wrapi(o[2] - (I.k[2] - 1) + x2, I.m[2]);
+      halo[x] = L[((int64_t)g0 * I.m[1] + g1) * I.m[2] + g2];
+    }
+    for (int e = tid; e < kp; e += kThreads) {
+      const int h = e >> 4, hf = (e >> 3) & 1, jj = e & 7;
+      offs2[e] = kernel_off((h >> 1) * 32 + (h & 1) * 16 + 2 * jj + hf, I, k);
+    }
+  } else {
+    typedef typename LowP<MODE>::h H;
+    H* e4 = reinterpret_cast<H*>(halo);
+    const float* D = I.D;
+    for (int x = tid; x < E123; x += kThreads) {
+      int x0 = x / E12, rem = x - x0 * E12;
+      int x1 = rem / I.E[2], x2 = rem - x1 * I.E[2];
+      const int g0 = wrapi(o[0] - (I.k[0] - 1) + x0, I.m[0]);
+      const int g1 = wrapi(o[1] - (I.k[1] - 1) + x1, I.m[1]);
+      const float* row = D + ((int64_t)g0 * I.m[1] + g1) * I.m[2];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const float v = (x2 >= d) ? row[wrapi(o[2] - (I.k[2] - 1) + x2 - d, I.m[2])] : 0.f;
+        e4[4 * x + d] = (H)v;
+      }
+    }
+    for (int e = tid; e < kp / 4; e += kThreads) offs2[e] = kernel_off(4 * e, I, k);
   }
   __syncthreads();
 
   const float ratio = (float)I.st->ratio;
   const int nkb = kp / 32;
-  const int nhs = 2 * nkb;  // half-steps of 8 MFMA k-steps (16 kernel offsets)
+  const int nhs = 2 * nkb;  // half-steps of 16 kernel offsets
   for (int u = wave; u < nrc * ncc; u += 4) {
     const int rc = u / ncc, cc = u % ncc;
     const int c0 = cg * CG + cc * kColUnit;
@@ -193,6 +255,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = (floatx16)(0.0f);
 
+    if constexpr (MODE == kFP32) {
     // V fragments: per (column block, offset block) 16 floats per lane in k-step
     // order, consumed in halves of 8 k-steps. Each iteration first takes the
     // operands loaded during the previous one, then issues the loads of the next
@@ -237,6 +300,46 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
         acc[1][1] = mfma32(a1[jj], b1[jj], acc[1][1]);
       }
     }
+    } else {
+    // reduced precision: one MFMA per (column block, row block) and 16 kernel offsets;
+    // A = V (16 bytes per lane, prepacked), B = four-offset runs of D from the
+    // expanded halo (two 8-byte LDS reads per row block)
+    typedef typename LowP<MODE>::v8 V8;
+    typedef typename LowP<MODE>::v4 V4;
+    const V4* e4 = reinterpret_cast<const V4*>(halo);
+    const uint4* vf0 = reinterpret_cast<const uint4*>(a.Vf_lo) + (size_t)(c0 / 32) * nhs * 64 + lane;
+    const uint4* vf1 = vf0 + (size_t)nhs * 64;
+    uint4 an0, an1;
+    V4 bn[2][2];
+    auto load_step = [&](int kk) {
+      an0 = vf0[(size_t)kk * 64];
+      an1 = vf1[(size_t)kk * 64];
+      const int2 ot = *reinterpret_cast<const int2*>(offs2 + kk * 4 + half * 2);
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib) {
+        bn[ib][0] = e4[base[ib] - ot.x];
+        bn[ib][1] = e4[base[ib] - ot.y];
+      }
+    };
+    load_step(0);
+    for (int kk = 0; kk < nhs; ++kk) {
+      V8 av0, av1, bv0, bv1;
+      __builtin_memcpy(&av0, &an0, 16);
+      __builtin_memcpy(&av1, &an1, 16);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        bv0[j] = bn[0][0][j];
+        bv0[4 + j] = bn[0][1][j];
+        bv1[j] = bn[1][0][j];
+        bv1[4 + j] = bn[1][1][j];
+      }
+      if (kk + 1 < nhs) load_step(kk + 1);
+      acc[0][0] = LowP<MODE>::mfma(av0, bv0, acc[0][0]);
+      acc[0][1] = LowP<MODE>::mfma(av0, bv1, acc[0][1]);
+      acc[1][0] = LowP<MODE>::mfma(av1, bv0, acc[1][0]);
+      acc[1][1] = LowP<MODE>::mfma(av1, bv1, acc[1][1]);
+    }
+    }
 
     // fused epilogue, four columns at a time
     float rsum = 0.f;
@@ -265,6 +368,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             float w = acc[cb][ib][4 * g + e];
+            if (MODE != kFP32) w += uo[e] + qo[e];  // W^t = W^{t-1} + A_k(L^t - L^{t-1}) V
             float unew, qnew;
             if (!valid[ib]) {
               w = 0.f;
@@ -332,11 +436,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
 // =====================================================================================
 constexpr int kMaxOwned = 16;  // box positions per thread (E123 <= 4096)
 
+template <int MODE>
 __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
   extern __shared__ float smem[];
   const int2 tt = a.tiles[blockIdx.x];
   const InstDev& I = a.inst[tt.x];
-  if (I.st->phase != kRun) return;
+  if (I.st->phase != kRun || !runs_iteration<MODE>(I, I.st)) return;
   const int kp = a.kp, k = a.k;
   const int sg = blockIdx.y;
   const int SGW = kp < kGroup ? kp : kGroup;
@@ -373,6 +478,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = (floatx16)(0.0f);
+    if constexpr (MODE == kFP32) {
     gcfloat4* va0 = gc4(a.Va) + (size_t)(s0 / 32) * nkb * 256 + lane * 4;
     gcfloat4* va1 = va0 + (size_t)nkb * 256;
     const size_t row0 = ((size_t)lt * (bm / 32) + rc * 2) * nkb;  // row group jb: (row0 + jb * nkb + cb)
@@ -422,6 +528,55 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
         acc[1][0] = mfma32(v1[jj], g[0][jj], acc[1][0]);
         acc[1][1] = mfma32(v1[jj], g[1][jj], acc[1][1]);
       }
+    }
+    } else {
+    // reduced precision: the contraction runs on the change of G since the previous
+    // iteration, dG = G^t - G^{t-1} = (s - 1) Q - U / ratio_prev, and the L-step adds
+    // it to the running A_k^*(G V^T)
+    typedef typename LowP<MODE>::v8 V8;
+    const float rp = (float)(1.0 / I.st->ratio_prev);
+    const uint4* va0 = reinterpret_cast<const uint4*>(a.Va_lo) + (size_t)(s0 / 32) * nkb * 128 + lane;
+    const uint4* va1 = va0 + (size_t)nkb * 128;
+    const size_t row0 = ((size_t)lt * (bm / 32) + rc * 2) * nkb;
+    float4 fu[2][2], fq[2][2], fs[2];
+    uint4 fv0, fv1;
+    auto load = [&](int h) {
+      const int cb = h >> 1, p = h & 1;
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb) {
+        const size_t o = (row0 + (size_t)jb * nkb + cb) * 256 + lane * 4 + 2 * p;
+        fu[jb][0] = U4[o];
+        fu[jb][1] = U4[o + 1];
+        fq[jb][0] = Q4[o];
+        fq[jb][1] = Q4[o + 1];
+      }
+      fs[0] = *gc4(S + cb * 32 + (2 * p) * 8 + half * 4);
+      fs[1] = *gc4(S + cb * 32 + (2 * p + 1) * 8 + half * 4);
+      fv0 = va0[(size_t)h * 64];
+      fv1 = va1[(size_t)h * 64];
+    };
+    load(0);
+    for (int h = 0; h < nhb; ++h) {
+      V8 g[2];
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          g[jb][4 * t + 0] = (fs[t].x - 1.f) * fq[jb][t].x - fu[jb][t].x * rp;
+          g[jb][4 * t + 1] = (fs[t].y - 1.f) * fq[jb][t].y - fu[jb][t].y * rp;
+          g[jb][4 * t + 2] = (fs[t].z - 1.f) * fq[jb][t].z - fu[jb][t].z * rp;
+          g[jb][4 * t + 3] = (fs[t].w - 1.f) * fq[jb][t].w - fu[jb][t].w * rp;
+        }
+      }
+      V8 v0, v1;
+      __builtin_memcpy(&v0, &fv0, 16);
+      __builtin_memcpy(&v1, &fv1, 16);
+      if (h + 1 < nhb) load(h + 1);
+      acc[0][0] = LowP<MODE>::mfma(v0, g[0], acc[0][0]);
+      acc[0][1] = LowP<MODE>::mfma(v0, g[1], acc[0][1]);
+      acc[1][0] = LowP<MODE>::mfma(v1, g[0], acc[1][0]);
+      acc[1][1] = LowP<MODE>::mfma(v1, g[1], acc[1][1]);
+    }
     }
     // stage H^T of this unit: Hs[s - S0][row]
 #pragma unroll
@@ -498,6 +653,8 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
     t0 = (int)(r / I.m[1]);
   }
   if (in && phase == kRun) {
+    // partials of this iteration's adjoint: the full A_k^*(G V^T), or on a reduced
+    // precision iteration its change since the previous one
     const int32_t* g0 = I.gtab + I.goff[0] + t0 * I.C[0];
     const int32_t* g1 = I.gtab + I.goff[1] + t1 * I.C[1];
     const int32_t* g2 = I.gtab + I.goff[2] + t2 * I.C[2];
@@ -527,7 +684,11 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
       I.L[t] = lv;
       acc = (double)lv * (double)lv;
     } else {
-      const float tk = T / (float)a.k;
+      float tk = T / (float)a.k;
+      if (I.prec != kFP32) {
+        if (!I.st->refresh) tk += I.T[t];
+        I.T[t] = tk;
+      }
       float lv;
       if (!obs) {
         lv = tk;
@@ -539,6 +700,7 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
       }
       const float old = I.L[t];
       I.L[t] = lv;
+      if (I.prec != kFP32) I.D[t] = lv - old;
       const double d = (double)lv - (double)old;
       acc = d * d;
     }
@@ -700,6 +862,7 @@ __global__ __launch_bounds__(kThreads) void k_colnorm(StageArgs a) {
       const double th = st->theta;
       const double thn = fmin(I.rho * th, I.theta_max);
       st->theta_cur = th;
+      st->ratio_prev = st->ratio;
       st->ratio = th / thn;
       st->theta = thn;
       st->refresh = (I.refresh_every <= 1) || (st->iters % I.refresh_every == 0) ||
@@ -737,6 +900,34 @@ __global__ void k_prep_v(const float* V, int k, int kp, float* Vf, float* Va) {
     {  // adjoint: b1 = offset block, b2 = column block
       const int s = b1 * 32 + (l & 31), c = b2 * 32 + acc_col(j, l >> 5);
       Va[e] = (s < k && c < k) ? V[(int64_t)s * k + c] : 0.f;
+    }
+  }
+}
+
+//   Vf_lo[((cb * nhs + kk) * 64 + l) * 8 + j] = V[16*kk + 8*(l/32) + j][cb*32 + l%32]
+//   Va_lo[(((sb * nkb + cb) * 2 + p) * 64 + l) * 8 + j] = V[sb*32 + l%32][cb*32 + acc_col(8p + j, l/32)]
+template <int MODE>
+__global__ void k_prep_v_lp(const float* V, int k, int kp, void* Vf_lo, void* Va_lo) {
+  typedef typename LowP<MODE>::h H;
+  H* vf = reinterpret_cast<H*>(Vf_lo);
+  H* va = reinterpret_cast<H*>(Va_lo);
+  const int nkb = kp / 32, nhs = kp / 16;
+  const int64_t n = (int64_t)kp * kp;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e & 7);
+    const int l = (int)((e >> 3) & 63);
+    const int64_t blk = e >> 9;
+    {
+      const int kk = (int)(blk % nhs), cb = (int)(blk / nhs);
+      const int s = 16 * kk + 8 * (l >> 5) + j, c = cb * 32 + (l & 31);
+      vf[e] = (H)((s < k && c < k) ? V[(int64_t)s * k + c] : 0.f);
+    }
+    {
+      const int p = (int)(blk & 1);
+      const int64_t sc = blk >> 1;
+      const int cb = (int)(sc % nkb), sb = (int)(sc / nkb);
+      const int s = sb * 32 + (l & 31), c = cb * 32 + acc_col(8 * p + j, l >> 5);
+      va[e] = (H)((s < k && c < k) ? V[(int64_t)s * k + c] : 0.f);
     }
   }
 }
@@ -824,20 +1015,36 @@ void launch_colnorm(const StageArgs& a, int nslices_total, hipStream_t st) {
   hipLaunchKernelGGL(k_colnorm, dim3(nslices_total), dim3(kThreads), 0, st, a);
 }
 
-void launch_adjoint(const StageArgs& a, int ntiles_total, int lds_floats, hipStream_t st) {
-  hipLaunchKernelGGL(k_adjoint, dim3(ntiles_total, a.nsg), dim3(kThreads), lds_floats * 4, st, a);
+void launch_adjoint(const StageArgs& a, int ntiles_total, int lds_floats, int mode, hipStream_t st) {
+  const dim3 g(ntiles_total, a.nsg), b(kThreads);
+  if (mode == kBF16)
+    hipLaunchKernelGGL(k_adjoint<kBF16>, g, b, lds_floats * 4, st, a);
+  else if (mode == kFP16)
+    hipLaunchKernelGGL(k_adjoint<kFP16>, g, b, lds_floats * 4, st, a);
+  else
+    hipLaunchKernelGGL(k_adjoint<kFP32>, g, b, lds_floats * 4, st, a);
 }
 
 void launch_lstep(const StageArgs& a, int nlblocks_total, hipStream_t st) {
   hipLaunchKernelGGL(k_lstep, dim3(nlblocks_total), dim3(kThreads), 0, st, a);
 }
 
-void launch_forward(const StageArgs& a, int ntiles_total, int lds_floats, hipStream_t st) {
-  hipLaunchKernelGGL(k_forward, dim3(ntiles_total, a.ncg), dim3(kThreads), lds_floats * 4, st, a);
+void launch_forward(const StageArgs& a, int ntiles_total, int lds_floats, int mode, hipStream_t st) {
+  const dim3 g(ntiles_total, a.ncg), b(kThreads);
+  if (mode == kBF16)
+    hipLaunchKernelGGL(k_forward<kBF16>, g, b, lds_floats * 4, st, a);
+  else if (mode == kFP16)
+    hipLaunchKernelGGL(k_forward<kFP16>, g, b, lds_floats * 4, st, a);
+  else
+    hipLaunchKernelGGL(k_forward<kFP32>, g, b, lds_floats * 4, st, a);
 }
 
-void launch_prep_v(const float* V, int k, int kp, float* Vf, float* Va, void*, void*, int, hipStream_t st) {
-  hipLaunchKernelGGL(k_prep_v, dim3(grid_for((int64_t)kp * kp, 4096)), dim3(kThreads), 0, st, V, k, kp, Vf, Va);
+void launch_prep_v(const float* V, int k, int kp, float* Vf, float* Va, void* Vf_lo, void* Va_lo, int prec,
+                   hipStream_t st) {
+  const dim3 g(grid_for((int64_t)kp * kp, 4096)), b(kThreads);
+  hipLaunchKernelGGL(k_prep_v, g, b, 0, st, V, k, kp, Vf, Va);
+  if (prec == kBF16) hipLaunchKernelGGL(k_prep_v_lp<kBF16>, g, b, 0, st, V, k, kp, Vf_lo, Va_lo);
+  if (prec == kFP16) hipLaunchKernelGGL(k_prep_v_lp<kFP16>, g, b, 0, st, V, k, kp, Vf_lo, Va_lo);
 }
 
 void launch_check_v(const float* V, int k, float* out, hipStream_t st) {

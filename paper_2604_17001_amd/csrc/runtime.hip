@@ -112,9 +112,12 @@ static int pow2ceil(int v) {
 }
 
 static int lds_forward_floats(const Plan& p, int kp) {
+  // FP32: halo + offset table; reduced precision: 4-wide expanded halo of 16-bit values
+  // (2 floats per position) + a quarter-size offset table; the larger of the two
   const int CG = std::min(kp, kGroup);
   const int nrc = p.bm / kRowUnit, ncc = CG / kColUnit;
-  return ((p.E123 + 3) & ~3) + kp + 2 * nrc * CG + nrc * ncc;
+  const int h32 = ((p.E123 + 3) & ~3) + kp, hlp = 2 * p.E123 + kp / 4;
+  return std::max(h32, hlp) + 2 * nrc * CG + nrc * ncc;
 }
 
 static int lds_adjoint_floats(const Plan& p, int kp) {
@@ -295,7 +298,11 @@ struct Group {
     const size_t n = (size_t)kp * kp;
     Vf.ensure(budget, n * 4);
     Va.ensure(budget, n * 4);
-    launch_prep_v(V, k, kp, Vf.as<float>(), Va.as<float>(), nullptr, nullptr, prec, st);
+    if (prec != kFP32) {
+      Vlo_f.ensure(budget, n * 2);
+      Vlo_a.ensure(budget, n * 2);
+    }
+    launch_prep_v(V, k, kp, Vf.as<float>(), Va.as<float>(), Vlo_f.p, Vlo_a.p, prec, st);
     HIPCK(hipGetLastError());
   }
 
@@ -332,6 +339,7 @@ struct Group {
     d.mtot = p.mtot;
     d.max_iter = mb->params.max_iter;
     d.refresh_every = mb->params.refresh_every;
+    d.prec = prec;
     d.lam = std::isinf(mb->params.lambda) ? 1e308 : mb->params.lambda;
     d.rho = mb->params.rho;
     d.theta_max = mb->params.theta_max;
@@ -353,7 +361,7 @@ struct Group {
     int32_t* gt = (int32_t*)take(p.gtab.size() * 4);
     d.gtab = gt;
     if (prec != kFP32) {
-      d.Lprev = (float*)take((size_t)p.mtot * 4);
+      d.D = (float*)take((size_t)p.mtot * 4);
       d.T = (float*)take((size_t)p.mtot * 4);
     }
     HIPCK(hipMemcpyAsync(gt, p.gtab.data(), p.gtab.size() * 4, hipMemcpyHostToDevice, st));
@@ -435,9 +443,11 @@ struct Group {
   void launch_round(hipStream_t st) {
     const StageArgs a = args();
     launch_colnorm(a, nslice_total, st);
-    launch_adjoint(a, ntiles_total, lds_adj, st);
+    launch_adjoint(a, ntiles_total, lds_adj, kFP32, st);
+    if (prec != kFP32) launch_adjoint(a, ntiles_total, lds_adj, prec, st);
     launch_lstep(a, nlblk_total, st);
-    launch_forward(a, ntiles_total, lds_fwd, st);
+    launch_forward(a, ntiles_total, lds_fwd, kFP32, st);
+    if (prec != kFP32) launch_forward(a, ntiles_total, lds_fwd, prec, st);
   }
 
   // one round with an event pair around each stage; returns after the events are read
@@ -451,13 +461,15 @@ struct Group {
     launch_colnorm(a, nslice_total, st);
     HIPCK(hipEventRecord(prof->ev[1], st));
     HIPCK(hipEventRecord(prof->ev[2], st));
-    launch_adjoint(a, ntiles_total, lds_adj, st);
+    launch_adjoint(a, ntiles_total, lds_adj, kFP32, st);
+    if (prec != kFP32) launch_adjoint(a, ntiles_total, lds_adj, prec, st);
     HIPCK(hipEventRecord(prof->ev[3], st));
     HIPCK(hipEventRecord(prof->ev[4], st));
     launch_lstep(a, nlblk_total, st);
     HIPCK(hipEventRecord(prof->ev[5], st));
     HIPCK(hipEventRecord(prof->ev[6], st));
-    launch_forward(a, ntiles_total, lds_fwd, st);
+    launch_forward(a, ntiles_total, lds_fwd, kFP32, st);
+    if (prec != kFP32) launch_forward(a, ntiles_total, lds_fwd, prec, st);
     HIPCK(hipEventRecord(prof->ev[7], st));
     HIPCK(hipEventSynchronize(prof->ev[7]));
     for (int i = 0; i < 4; ++i) {
@@ -616,7 +628,13 @@ static void check_params(const icnnm_params* p) {
   if (p->max_iter < 0) throw Error(ICNNM_E_INVALID, "max_iter must be >= 0");
   if (!(p->tol >= 0)) throw Error(ICNNM_E_INVALID, "tol must be >= 0");
   if (p->precision < 0 || p->precision > 2) throw Error(ICNNM_E_INVALID, "unknown precision");
-  if (p->precision != 0) throw Error(ICNNM_E_INVALID, "reduced precision is not built in this library yet");
+  if (p->precision != 0 && p->refresh_every < 1) throw Error(ICNNM_E_INVALID, "refresh_every must be >= 1");
+}
+
+// the reduced-precision forward reads runs of four consecutive innermost kernel offsets
+static void check_precision_shape(const int kd[3], const icnnm_params* p) {
+  if (p->precision != 0 && kd[2] % 4 != 0)
+    throw Error(ICNNM_E_INVALID, "BF16/FP16 contractions need the innermost kernel dimension to be a multiple of 4");
 }
 
 static void check_v(icnnm_ctx* c, const float* V, int k, hipStream_t st) {
@@ -663,6 +681,7 @@ static icnnm_status do_solve(icnnm_ctx* c, const icnnm_shape* shape, const float
   int m[3], kd[3];
   normalize_shape(shape, m, kd);
   check_params(params);
+  check_precision_shape(kd, params);
   if (!M || !mask || !V || !L_out) throw Error(ICNNM_E_INVALID, "NULL array argument");
   std::lock_guard<std::recursive_mutex> lock(c->mu);
   hipStream_t st = enter(c, user_stream);
@@ -758,6 +777,7 @@ static icnnm_status do_solve_batch(icnnm_ctx* c, int count, const icnnm_shape* s
     int m[3], kd[3];
     normalize_shape(&shapes[i], m, kd);
     if (i == 0) std::copy(kd, kd + 3, kd0);
+    check_precision_shape(kd, params);
     if (!std::equal(kd, kd + 3, kd0)) throw Error(ICNNM_E_INVALID, "batch instances must share the kernel size");
     if (!Ms[i] || !masks[i] || !Louts[i]) throw Error(ICNNM_E_INVALID, "NULL array in batch");
     auto mb = std::make_unique<Member>();
@@ -1045,6 +1065,7 @@ static icnnm_status do_submit(icnnm_ctx* c, const icnnm_shape* shape, const floa
   Request r{};
   normalize_shape(shape, r.m, r.kd);
   check_params(params);
+  check_precision_shape(r.kd, params);
   if (!M || !mask || !V || !L_out) throw Error(ICNNM_E_INVALID, "NULL array argument");
   r.shape = *shape;
   r.M = M;

@@ -1,0 +1,110 @@
+"""Reduced-precision form: both contractions run on BF16 or FP16 MFMA (FP32
+accumulate) on the change of their operand since the previous iteration, with a
+full FP32 evaluation every refresh_every iterations and at the last one.
+Tolerance: relative Frobenius error <= 1e-3 against the FP64 oracle at equal
+iteration counts; observed entries stay bit-exact (lambda = inf)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import icnnm_ref as O
+from paper_2604_17001_amd import icnnm, inputs
+
+pytestmark = pytest.mark.gpu
+TOL_LP = 1e-3
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def _case(dims, kdims, pm, seed, b=6):
+    prob = inputs.random_problem(dims, kdims, pm, seed)
+    V, _ = O.learn(inputs.random_refs(dims, b, seed), kdims)
+    return prob, V.astype(np.float32)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("dims,kdims,seed", [((16, 16, 8), (4, 4, 4), 1), ((24, 20, 16), (5, 3, 8), 2),
+                                             ((9, 33), (3, 4), 3)])
+def test_reduced_precision_parity(lib, prec, dims, kdims, seed):
+    prob, V32 = _case(dims, kdims, 0.4, seed)
+    iters = 60
+    print(f"[gpu] {prec} dims={dims} kdims={kdims}", flush=True)
+    L, info = lib.solve(_dev(prob.M), _dev(prob.mask), _dev(V32), kdims, max_iter=iters, precision=prec)
+    L = L.cpu().numpy()
+    Lo, _ = O.solve(prob.M, prob.mask, V32.astype(np.float64), kdims, iters)
+    err = _rel(L, Lo)
+    print(f"[gpu] {prec} rel.err {err:.3e}", flush=True)
+    assert err <= TOL_LP
+    assert np.array_equal(L[prob.mask != 0], prob.M[prob.mask != 0])
+    assert info["iters"] == iters
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_refresh_every_iteration_is_fp32(lib, prec):
+    prob, V32 = _case((16, 16, 8), (4, 4, 4), 0.4, 4)
+    L1, _ = lib.solve(_dev(prob.M), _dev(prob.mask), _dev(V32), prob.kdims, max_iter=30, precision=prec,
+                      refresh_every=1)
+    L0, _ = lib.solve(_dev(prob.M), _dev(prob.mask), _dev(V32), prob.kdims, max_iter=30)
+    assert np.array_equal(L1.cpu().numpy(), L0.cpu().numpy())
+
+
+def test_refresh_improves_accuracy(lib):
+    prob, V32 = _case((16, 16, 8), (4, 4, 4), 0.4, 5)
+    Lo, _ = O.solve(prob.M, prob.mask, V32.astype(np.float64), prob.kdims, 80)
+    errs = {}
+    for r in (5, 80):
+        L, _ = lib.solve(_dev(prob.M), _dev(prob.mask), _dev(V32), prob.kdims, max_iter=80, precision="bf16",
+                         refresh_every=r)
+        errs[r] = _rel(L.cpu().numpy(), Lo)
+    print(f"[gpu] bf16 rel.err with refresh every 5: {errs[5]:.3e}, without refresh: {errs[80]:.3e}", flush=True)
+    # the periodic FP32 evaluation is what keeps the reduced-precision path inside 1e-3
+    assert errs[5] <= TOL_LP
+    assert errs[80] > 10 * errs[5]
+
+
+def test_precision_needs_innermost_kernel_multiple_of_4(lib):
+    prob, V32 = _case((12, 10, 8), (3, 3, 2), 0.4, 6)
+    with pytest.raises(icnnm.IcnnmError) as ei:
+        lib.solve(_dev(prob.M), _dev(prob.mask), _dev(V32), prob.kdims, max_iter=5, precision="bf16")
+    assert ei.value.code == icnnm.E_INVALID
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("name,factory", [("c1", inputs.c1_plain), ("c2", inputs.c2_plain)])
+def test_config_reduced_precision_vs_stored_oracle(lib, prec, name, factory):
+    if not os.path.exists(os.path.join(GOLD, f"{name}_L.npy")):
+        pytest.skip("stored oracle result missing")
+    wl = factory(b_refs=0)
+    p = wl.problems[0]
+    V32 = np.load(os.path.join(GOLD, f"{name}_V.npy"))
+    Lo = np.load(os.path.join(GOLD, f"{name}_L.npy"))
+    print(f"[gpu] {name} {prec}", flush=True)
+    L, info = lib.solve(_dev(p.M), _dev(p.mask), _dev(V32), wl.kdims, max_iter=wl.iters, precision=prec)
+    L = L.cpu().numpy()
+    err = _rel(L, Lo)
+    print(f"[gpu] {name} {prec} rel.err {err:.3e}", flush=True)
+    assert err <= TOL_LP
+    assert np.array_equal(L[p.mask != 0], p.M[p.mask != 0])
+
+
+def test_batch_reduced_precision(lib):
+    kd = (4, 4, 4)
+    shapes = [(16, 12, 8), (24, 16, 8), (12, 12, 4), (20, 9, 16)]
+    probs = [inputs.random_problem(d, kd, 0.35, seed=130 + i) for i, d in enumerate(shapes)]
+    V, _ = O.learn([inputs.random_refs(shapes[0], 1, seed=140)[0]], kd)
+    V32 = V.astype(np.float32)
+    Ls, infos = lib.solve_batch([_dev(p.M) for p in probs], [_dev(p.mask) for p in probs], _dev(V32), kd,
+                                max_iter=40, precision="bf16")
+    for p, L in zip(probs, Ls):
+        Lo, _ = O.solve(p.M, p.mask, V32.astype(np.float64), kd, 40)
+        assert _rel(L.cpu().numpy(), Lo) <= TOL_LP

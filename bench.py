@@ -45,7 +45,107 @@ def _kernel_src_hash():
 
 def _workload(name):
     from paper_2604_17001_amd import inputs
-    return {"c1": inputs.c1_plain, "c2": inputs.c2_plain, "c3": inputs.c3_precision}[name]()
+    return {"c1": inputs.c1_plain, "c2": inputs.c2_plain, "c3": inputs.c3_precision, "c4": inputs.c4_batch}[name]()
+
+
+def _batch_main(args):
+    """Batching form: 64 uneven instances (extents {32..128}^2 x {8,16,32}, 8x8x4 kernel,
+    one shared V) solved in joint launches; a step is one solve of the whole batch."""
+    import torch
+    from paper_2604_17001_amd import icnnm
+    wl = _workload("c4")
+    iters = args.iters or wl.iters
+    lib = icnnm.Library.get()
+    dev = torch.device("cuda", 0)
+    Ms = [torch.from_numpy(p.M).to(dev) for p in wl.problems]
+    masks = [torch.from_numpy(p.mask).to(dev) for p in wl.problems]
+    outs = [torch.empty_like(x) for x in Ms]
+    V, _ = lib.learn_eigvecs([torch.from_numpy(r).to(dev) for r in wl.refs], wl.kdims)
+    kw = dict(max_iter=iters, precision=args.precision)
+    for _ in range(args.warmup):
+        lib.solve_batch(Ms, masks, V, wl.kdims, outs=outs, **kw)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        _, infos = lib.solve_batch(Ms, masks, V, wl.kdims, outs=outs, **kw)
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n = len(wl.problems)
+    msum = sum(p.m for p in wl.problems)
+    # one-at-a-time FP32 solves of the same instances, the baseline form
+    t1 = time.perf_counter()
+    for M, mk, o in zip(Ms, masks, outs):
+        lib.solve(M, mk, V, wl.kdims, out=o, max_iter=iters)
+    torch.cuda.synchronize()
+    single = n / (time.perf_counter() - t1)
+    flops = 4.0 * msum * wl.problems[0].k ** 2 * iters
+    out = {"metric": "solved tensors/s (uneven batch) at rel.err<=1e-3 vs FP64 oracle",
+           "value": round(n * args.steps / dt, 3), "unit": "tensors/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else args.precision,
+           "data": "synthetic",
+           "config": {"workload": wl.name, "instances": n, "sum_m": msum, "kdims": list(wl.kdims),
+                      "iters": iters, "precision": args.precision},
+           "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+           "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+           "tflops_effective": round(flops * args.steps / dt / 1e12, 2),
+           "fp32_one_at_a_time_tensors_per_s": round(single, 3),
+           "iters_run": [i["iters"] for i in infos][:4]}
+    print(json.dumps(out), flush=True)
+
+
+def _serve_main(args):
+    """Serving form: Poisson arrivals of batch-type requests with a share of 128x128x32
+    requests at a 16x16x4 kernel; each retired at max(r_primal, r_change) <= tol.
+    Reports tensors/s over the run and arrival-to-retirement latency percentiles."""
+    import torch
+    from paper_2604_17001_amd import icnnm, inputs
+    rate, n = args.rate, args.requests
+    arrivals, probs = inputs.serve_requests(n, rate, large_frac=args.large_frac)
+    lib = icnnm.Library(budget=int(args.budget_gb * (1 << 30)))
+    dev = torch.device("cuda", 0)
+    banks = {}
+    for kd, gen in [((8, 8, 4), inputs.c4_batch), ((16, 16, 4), inputs.c3_precision)]:
+        if any(tuple(p.kdims) == kd for p in probs):
+            refs = gen(b_refs=4).refs if kd == (16, 16, 4) else gen(count=1).refs
+            banks[kd] = lib.learn_eigvecs([torch.from_numpy(r).to(dev) for r in refs], kd)[0]
+    Ms = [torch.from_numpy(p.M).to(dev) for p in probs]
+    masks = [torch.from_numpy(p.mask).to(dev) for p in probs]
+    outs = [torch.empty_like(x) for x in Ms]
+    torch.cuda.synchronize()
+    kw = dict(max_iter=args.iters or 1000, tol=args.tol, precision=args.precision)
+    t0 = time.perf_counter()
+    tickets, done, lat, iters = {}, {}, [], []
+    nxt = 0
+    while len(done) < n:
+        now = time.perf_counter() - t0
+        while nxt < n and arrivals[nxt] <= now:
+            p = probs[nxt]
+            tickets[lib.submit(Ms[nxt], masks[nxt], banks[tuple(p.kdims)], p.kdims, outs[nxt], **kw)] = nxt
+            nxt += 1
+        for t, i in list(tickets.items()):
+            rc, info = lib.poll(t)
+            if rc != icnnm.PENDING:
+                done[i] = rc
+                lat.append(time.perf_counter() - t0 - arrivals[i])
+                iters.append(info["iters"])
+                del tickets[t]
+        time.sleep(0.0005)
+    total = time.perf_counter() - t0
+    lib.close()
+    lat_ms = np.array(lat) * 1e3
+    out = {"metric": "served tensors/s at residual <= tol (continuous batching)", "value": round(n / total, 3),
+           "unit": "tensors/s", "n_gpus": 1, "steps": n, "warmup": 0, "ms_per_step": round(1e3 * total / n, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.precision,
+           "data": "synthetic",
+           "config": {"workload": "c5_serve_poisson", "rate_req_s": rate, "requests": n,
+                      "large_frac": args.large_frac, "tol": args.tol, "budget_gb": args.budget_gb},
+           "p50_ms": round(float(np.percentile(lat_ms, 50)), 2), "p99_ms": round(float(np.percentile(lat_ms, 99)), 2),
+           "ok": int(sum(1 for v in done.values() if v == icnnm.OK)), "mean_iters": round(float(np.mean(iters)), 1)}
+    print(json.dumps(out), flush=True)
 
 
 def _cpu_baseline(prob, V, kdims, iters, sample_iters):
@@ -69,7 +169,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--rate", type=float, default=10.0, help="c5: Poisson arrival rate (req/s)")
+    ap.add_argument("--requests", type=int, default=64, help="c5: number of requests")
+    ap.add_argument("--large-frac", type=float, default=0.10, help="c5: share of 128x128x32 requests")
+    ap.add_argument("--tol", type=float, default=1e-4, help="c5: retirement residual")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="c5: HBM budget of the server")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--cpu-sample-iters", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -82,6 +187,11 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "independent instances shard across GPUs without communication", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c4":
+        return _batch_main(args)
+    if args.workload == "c5":
+        return _serve_main(args)
 
     import torch
     from paper_2604_17001_amd import icnnm

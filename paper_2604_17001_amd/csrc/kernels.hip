@@ -341,29 +341,60 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
     }
     }
 
-    // fused epilogue, four columns at a time
+    // fused epilogue over the four 32x32 pieces (cb, ib) of the unit; the U/Q loads
+    // of a piece are issued two pieces ahead so that their latency overlaps the
+    // arithmetic and stores of the pieces before it
     float rsum = 0.f;
+    float4 bu[2][4], bq[2][4];
+    auto load_piece = [&](int pc, int slot) {
+      const int cb = pc >> 1, ib = pc & 1;
+      const size_t sidx = ((((size_t)lt * (I.bm / 32) + rc * 2 + ib) * nkb + c0 / 32 + cb) * 64 + lane) * 4;
+      gcfloat4* Up = gc4(I.U) + sidx;
+      gcfloat4* Qp = gc4(I.Q) + sidx;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        bu[slot][g] = Up[g];
+        bq[slot][g] = Qp[g];
+      }
+    };
+    if (!init) {
+      load_piece(0, 0);
+      load_piece(1, 1);
+    }
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
       const int cblk = c0 / 32 + cb;
+      float4 s4[4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        s4[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (!init) s4[g] = *gc4(I.s + cblk * 32 + g * 8 + half * 4);
+      }
       float qs[16], ws[16];
 #pragma unroll
       for (int v = 0; v < 16; ++v) qs[v] = ws[v] = 0.f;
 #pragma unroll
       for (int ib = 0; ib < 2; ++ib) {
-        const size_t sidx = ((((size_t)lt * (I.bm / 32) + rc * 2 + ib) * nkb + cblk) * 64 + lane) * 4;
-        float4* Up = reinterpret_cast<float4*>(I.U) + sidx;
-        float4* Qp = reinterpret_cast<float4*>(I.Q) + sidx;
+        const int pc = cb * 2 + ib, slot = pc & 1;
+        float4 u4s[4], q4s[4];
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-          float4 u4 = make_float4(0.f, 0.f, 0.f, 0.f), q4 = u4, s4 = u4;
+          u4s[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+          q4s[g] = u4s[g];
           if (!init) {
-            u4 = Up[g];
-            q4 = Qp[g];
-            s4 = *reinterpret_cast<const float4*>(I.s + cblk * 32 + g * 8 + half * 4);
+            u4s[g] = bu[slot][g];
+            q4s[g] = bq[slot][g];
           }
+        }
+        if (!init && pc + 2 < 4) load_piece(pc + 2, slot);
+        const size_t sidx = ((((size_t)lt * (I.bm / 32) + rc * 2 + ib) * nkb + cblk) * 64 + lane) * 4;
+        gfloat4* Up = g4(I.U) + sidx;
+        gfloat4* Qp = g4(I.Q) + sidx;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const float4 u4 = u4s[g], q4 = q4s[g], sv4 = s4[g];
           const float uo[4] = {u4.x, u4.y, u4.z, u4.w}, qo[4] = {q4.x, q4.y, q4.z, q4.w};
-          const float sv[4] = {s4.x, s4.y, s4.z, s4.w};
+          const float sv[4] = {sv4.x, sv4.y, sv4.z, sv4.w};
           float un[4], qn[4];
 #pragma unroll
           for (int e = 0; e < 4; ++e) {

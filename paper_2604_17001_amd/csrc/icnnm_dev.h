@@ -85,7 +85,7 @@ struct StageArgs {
 };
 
 // Launchers (defined in kernels.hip). All take the stream to launch on.
-void launch_colnorm(const StageArgs& a, int nslices_total, hipStream_t st);
+void launch_colnorm(const StageArgs& a, int nslices_total, int ninst, hipStream_t st);
 // mode 0: FP32 contraction (initialisation, FP32 solves, refresh iterations);
 // mode 1 / 2: BF16 / FP16 contraction of the change since the previous iteration
 void launch_adjoint(const StageArgs& a, int ntiles_total, int lds_floats, int mode, hipStream_t st);

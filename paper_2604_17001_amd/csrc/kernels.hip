@@ -690,19 +690,22 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
     const int32_t* g1 = I.gtab + I.goff[1] + t1 * I.C[1];
     const int32_t* g2 = I.gtab + I.goff[2] + t2 * I.C[2];
     const int nsg = a.nsg;
-    const int C12 = I.C[1] * I.C[2];
-    const int total = I.C[0] * C12 * nsg;
-    for (int idx = sub; idx < total; idx += kLanesPerElem) {
-      const int g = idx % nsg;
-      const int c = idx / nsg;
-      const int c2 = c % I.C[2];
-      const int c1 = (c / I.C[2]) % I.C[1];
-      const int c0 = c / C12;
-      const int e0 = g0[c0], e1 = g1[c1], e2 = g2[c2];
-      if ((e0 | e1 | e2) < 0) continue;
-      const int tile = ((e0 >> 16) * I.nt[1] + (e1 >> 16)) * I.nt[2] + (e2 >> 16);
-      const int pos = ((e0 & 0xffff) * I.E[1] + (e1 & 0xffff)) * I.E[2] + (e2 & 0xffff);
-      T += I.part[((size_t)tile * nsg + g) * I.E123 + pos];
+    // lane `sub` takes the (c0, c1) pairs congruent to it modulo kLanesPerElem and
+    // sums all c2 and offset groups of each, in a fixed order
+    const int C1 = I.C[1], C2 = I.C[2];
+    const int npair = I.C[0] * C1;
+    for (int pr = sub; pr < npair; pr += kLanesPerElem) {
+      const int c0 = pr / C1, c1 = pr - c0 * C1;
+      const int e0 = g0[c0], e1 = g1[c1];
+      if ((e0 | e1) < 0) continue;
+      const int tb = ((e0 >> 16) * I.nt[1] + (e1 >> 16)) * I.nt[2];
+      const int pb = ((e0 & 0xffff) * I.E[1] + (e1 & 0xffff)) * I.E[2];
+      for (int c2 = 0; c2 < C2; ++c2) {
+        const int e2 = g2[c2];
+        if (e2 < 0) break;
+        const float* pp = I.part + ((size_t)(tb + (e2 >> 16)) * nsg) * I.E123 + pb + (e2 & 0xffff);
+        for (int g = 0; g < nsg; ++g) T += pp[(size_t)g * I.E123];
+      }
     }
   }
 #pragma unroll
@@ -746,30 +749,19 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
 }
 
 // =====================================================================================
-// colnorm: FP64 reduction of the per-tile partials. Block b of an instance reduces
-// columns 4b..4b+3 (one wavefront per column, lanes over tiles, fixed shuffle tree)
-// and a share of the scalar partials; the last arriving block finishes: column norms
-// -> shrink factors, penalty schedule, residuals of the previous iteration, stopping.
+// colnorm, two launches. k_colnorm_reduce: block b of an instance reduces columns
+// 4b..4b+3 in FP64 (one wavefront per column, lanes over tiles, fixed shuffle tree)
+// and a share of the scalar partials. k_colnorm_finish (one block per instance):
+// column norms -> shrink factors (Z-step), penalty schedule, residuals of the
+// previous iteration, stopping decision, phase changes. The kernel boundary orders
+// the two, so no device-scope fences or counters are needed.
 // =====================================================================================
-__global__ __launch_bounds__(kThreads) void k_colnorm(StageArgs a) {
+__global__ __launch_bounds__(kThreads) void k_colnorm_reduce(StageArgs a) {
   const int2 sl = a.slices[blockIdx.x];
   const InstDev& I = a.inst[sl.x];
-  InstState* st = I.st;
-  const int phase = st->phase;
+  const int phase = I.st->phase;
+  if (phase != kInit && phase != kRun) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (phase == kDone) return;
-  // a new instance only moves to initialisation; the move is made by the last
-  // arriving block so that no block of this launch sees the new phase
-  if (phase == kNew) {
-    if (tid == 0) {
-      __threadfence();
-      if (atomicAdd(&st->counter, 1u) == (unsigned)I.nslice - 1u) {
-        st->counter = 0u;
-        st->phase = kInit;
-      }
-    }
-    return;
-  }
   const int kp = a.kp;
   const int nt = I.ntiles;
   double* colsum = I.slice;              // [kp][2]: sum Q^2, sum W^2
@@ -794,40 +786,41 @@ __global__ __launch_bounds__(kThreads) void k_colnorm(StageArgs a) {
       colsum[2 * c + 1] = w;
     }
   }
-  {
-    __shared__ double red[2][kThreads / 64];
-    const int nr = nt * a.ncg;
-    const int rch = (nr + I.nslice - 1) / I.nslice, lch = (I.nlblk + I.nslice - 1) / I.nslice;
-    double r = 0.0, dl = 0.0;
-    for (int i = sl.y * rch + tid; i < min(nr, (sl.y + 1) * rch); i += kThreads) r += (double)I.rpart[i];
-    for (int i = sl.y * lch + tid; i < min(I.nlblk, (sl.y + 1) * lch); i += kThreads) dl += I.dlpart[i];
+  __shared__ double red[2][kThreads / 64];
+  const int nr = nt * a.ncg;
+  const int rch = (nr + I.nslice - 1) / I.nslice, lch = (I.nlblk + I.nslice - 1) / I.nslice;
+  double r = 0.0, dl = 0.0;
+  for (int i = sl.y * rch + tid; i < min(nr, (sl.y + 1) * rch); i += kThreads) r += (double)I.rpart[i];
+  for (int i = sl.y * lch + tid; i < min(I.nlblk, (sl.y + 1) * lch); i += kThreads) dl += I.dlpart[i];
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      r += __shfl_xor(r, o, 64);
-      dl += __shfl_xor(dl, o, 64);
-    }
-    if (lane == 0) {
-      red[0][wave] = r;
-      red[1][wave] = dl;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      scal[2 * sl.y] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
-      scal[2 * sl.y + 1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
-    }
+  for (int o = 1; o < 64; o <<= 1) {
+    r += __shfl_xor(r, o, 64);
+    dl += __shfl_xor(dl, o, 64);
   }
-  // last-arriving block of this instance finishes
-  __shared__ int last;
+  if (lane == 0) {
+    red[0][wave] = r;
+    red[1][wave] = dl;
+  }
   __syncthreads();
   if (tid == 0) {
-    __threadfence();
-    const unsigned prev = atomicAdd(&st->counter, 1u);
-    last = (prev == (unsigned)I.nslice - 1u);
+    scal[2 * sl.y] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+    scal[2 * sl.y + 1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
   }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
+}
 
+__global__ __launch_bounds__(kThreads) void k_colnorm_finish(StageArgs a) {
+  const InstDev& I = a.inst[blockIdx.x];
+  InstState* st = I.st;
+  const int phase = st->phase;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (phase == kDone) return;
+  if (phase == kNew) {
+    if (tid == 0) st->phase = kInit;
+    return;
+  }
+  const int kp = a.kp;
+  const double* colsum = I.slice;
+  const double* scal = I.slice + 2 * kp;
   __shared__ double sh_obj[kThreads / 64], sh_max[kThreads / 64], sh_sc[2];
   double obj = 0.0, mx = 0.0;
   for (int c = tid; c < kp; c += kThreads) {
@@ -855,7 +848,6 @@ __global__ __launch_bounds__(kThreads) void k_colnorm(StageArgs a) {
   __syncthreads();
   __shared__ int go_on;
   if (tid == 0) {
-    st->counter = 0u;
     const double objective = ((sh_obj[0] + sh_obj[1]) + sh_obj[2]) + sh_obj[3];
     const double maxn = fmax(fmax(sh_max[0], sh_max[1]), fmax(sh_max[2], sh_max[3]));
     int go = 1;
@@ -1042,8 +1034,9 @@ static inline int grid_for(int64_t n, int cap = 65536) {
   return (int)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
-void launch_colnorm(const StageArgs& a, int nslices_total, hipStream_t st) {
-  hipLaunchKernelGGL(k_colnorm, dim3(nslices_total), dim3(kThreads), 0, st, a);
+void launch_colnorm(const StageArgs& a, int nslices_total, int ninst, hipStream_t st) {
+  hipLaunchKernelGGL(k_colnorm_reduce, dim3(nslices_total), dim3(kThreads), 0, st, a);
+  hipLaunchKernelGGL(k_colnorm_finish, dim3(ninst), dim3(kThreads), 0, st, a);
 }
 
 void launch_adjoint(const StageArgs& a, int ntiles_total, int lds_floats, int mode, hipStream_t st) {

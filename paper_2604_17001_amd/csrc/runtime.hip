@@ -442,7 +442,7 @@ struct Group {
 
   void launch_round(hipStream_t st) {
     const StageArgs a = args();
-    launch_colnorm(a, nslice_total, st);
+    launch_colnorm(a, nslice_total, (int)members.size(), st);
     launch_adjoint(a, ntiles_total, lds_adj, kFP32, st);
     if (prec != kFP32) launch_adjoint(a, ntiles_total, lds_adj, prec, st);
     launch_lstep(a, nlblk_total, st);
@@ -458,7 +458,7 @@ struct Group {
       for (auto& e : prof->ev) HIPCK(hipEventCreate(&e));
     }
     HIPCK(hipEventRecord(prof->ev[0], st));
-    launch_colnorm(a, nslice_total, st);
+    launch_colnorm(a, nslice_total, (int)members.size(), st);
     HIPCK(hipEventRecord(prof->ev[1], st));
     HIPCK(hipEventRecord(prof->ev[2], st));
     launch_adjoint(a, ntiles_total, lds_adj, kFP32, st);

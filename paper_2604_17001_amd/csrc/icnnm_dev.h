@@ -77,6 +77,7 @@ struct StageArgs {
   const int2* slices;    // (instance, slice) for the column-norm reduction
   const float* Vf;       // forward operand layout of V (FP32)
   const float* Va;       // adjoint operand layout of V (FP32)
+  const float* Vp;       // V zero-padded to kp x kp, row-major (FP32)
   const void* Vf_lo;     // forward operand layout of V (BF16/FP16)
   const void* Va_lo;     // adjoint operand layout of V (BF16/FP16)
   int32_t kp, k, nsg, ncg;
@@ -91,8 +92,10 @@ void launch_colnorm(const StageArgs& a, int nslices_total, int ninst, hipStream_
 void launch_adjoint(const StageArgs& a, int ntiles_total, int lds_floats, int mode, hipStream_t st);
 void launch_lstep(const StageArgs& a, int nlblocks_total, hipStream_t st);
 void launch_forward(const StageArgs& a, int ntiles_total, int lds_floats, int mode, hipStream_t st);
-void launch_prep_v(const float* V, int k, int kp, float* Vf, float* Va, void* Vf_lo,
+void launch_prep_v(const float* V, int k, int kp, float* Vf, float* Va, float* Vp, void* Vf_lo,
                    void* Va_lo, int prec, hipStream_t st);
+// adjoint tiled for large kernels (kp >= 512, 128-row tiles)
+void launch_adjoint_big(const StageArgs& a, int ntiles_total, int mode, hipStream_t st);
 void launch_check_v(const float* V, int k, float* out_maxdev, hipStream_t st);
 void launch_autocorr(const float* L, const int32_t* m, const int32_t* k, double* R,
                      hipStream_t st);

@@ -14,6 +14,8 @@
 //   lane l supplies A[l%32][l/32] and B[l/32][l%32].
 #include "icnnm_dev.h"
 
+#include <algorithm>
+
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
@@ -467,6 +469,37 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
 // =====================================================================================
 constexpr int kMaxOwned = 16;  // box positions per thread (E123 <= 4096)
 
+// col2im gather: thread-owned box position x (box coordinates) receives
+// H[j = x - (k - 1) + s][s] for the staged kernel offsets s in [S0, S1) whose row j
+// lies inside the tile; Hs[s - S0][row] holds the staged H^T. Fixed order.
+__device__ __forceinline__ void gather_round(const InstDev& I, const float* Hs, int hstride, int S0, int S1,
+                                             float* tacc) {
+  const int k0 = I.k[0], k1 = I.k[1], k2 = I.k[2], k12 = k1 * k2;
+  const int E123 = I.E123, E12 = I.E[1] * I.E[2];
+#pragma unroll
+  for (int i = 0; i < kMaxOwned; ++i) {
+    const int x = threadIdx.x + i * kThreads;
+    if (x >= E123) break;
+    const int x0 = x / E12, rem = x - x0 * E12;
+    const int x1 = rem / I.E[2], x2 = rem - x1 * I.E[2];
+    // s_d in [lo_d, hi_d) keeps j_d = x_d - (k_d - 1) + s_d inside [0, b_d)
+    const int lo0 = max(0, k0 - 1 - x0), hi0 = min(k0, k0 - 1 - x0 + I.b[0]);
+    const int lo1 = max(0, k1 - 1 - x1), hi1 = min(k1, k1 - 1 - x1 + I.b[1]);
+    const int lo2 = max(0, k2 - 1 - x2), hi2 = min(k2, k2 - 1 - x2 + I.b[2]);
+    float sum = tacc[i];
+    for (int p = max(lo0, S0 / k12); p < hi0 && p * k12 < S1; ++p) {
+      const int j0 = x0 - (k0 - 1) + p;
+      for (int q = lo1; q < hi1; ++q) {
+        const int spq = (p * k1 + q) * k2;
+        const int r0 = max(lo2, S0 - spq), r1 = min(hi2, S1 - spq);
+        const int jrow = (j0 * I.b[1] + (x1 - (k1 - 1) + q)) * I.b[2] + (x2 - (k2 - 1));
+        for (int r = r0; r < r1; ++r) sum += Hs[(spq + r - S0) * hstride + jrow + r];
+      }
+    }
+    tacc[i] = sum;
+  }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
   extern __shared__ float smem[];
@@ -488,7 +521,6 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
 
   // owned box positions and their valid kernel-offset ranges per dimension
   const int E123 = I.E123;
-  const int k0 = I.k[0], k1 = I.k[1], k2 = I.k[2], k12 = k1 * k2;
   float tacc[kMaxOwned];
 #pragma unroll
   for (int i = 0; i < kMaxOwned; ++i) tacc[i] = 0.f;
@@ -621,31 +653,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
         }
     }
     __syncthreads();
-    // gather: box position t' (box coordinates) receives H[j = t' - (k-1) + s][s]
-    // for the kernel offsets s of this round with j inside the tile
-    const int S1 = min(S0 + spr, k);
-#pragma unroll
-    for (int i = 0; i < kMaxOwned; ++i) {
-      const int x = tid + i * kThreads;
-      if (x >= E123) break;
-      const int x0 = x / (I.E[1] * I.E[2]), rem = x - x0 * (I.E[1] * I.E[2]);
-      const int x1 = rem / I.E[2], x2 = rem - x1 * I.E[2];
-      // s_d in [lo_d, hi_d) keeps j_d = x_d - (k_d - 1) + s_d inside [0, b_d)
-      const int lo0 = max(0, k0 - 1 - x0), hi0 = min(k0, k0 - 1 - x0 + I.b[0]);
-      const int lo1 = max(0, k1 - 1 - x1), hi1 = min(k1, k1 - 1 - x1 + I.b[1]);
-      const int lo2 = max(0, k2 - 1 - x2), hi2 = min(k2, k2 - 1 - x2 + I.b[2]);
-      float sum = tacc[i];
-      for (int p = max(lo0, S0 / k12); p < hi0 && p * k12 < S1; ++p) {
-        const int j0 = x0 - (k0 - 1) + p;
-        for (int q = lo1; q < hi1; ++q) {
-          const int spq = (p * k1 + q) * k2;
-          const int r0 = max(lo2, S0 - spq), r1 = min(hi2, S1 - spq);
-          const int jrow = (j0 * I.b[1] + (x1 - (k1 - 1) + q)) * I.b[2] + (x2 - (k2 - 1));
-          for (int r = r0; r < r1; ++r) sum += Hs[(spq + r - S0) * hstride + jrow + r];
-        }
-      }
-      tacc[i] = sum;
-    }
+    gather_round(I, Hs, hstride, S0, min(S0 + spr, k), tacc);
     __syncthreads();
   }
   float* dst = I.part + ((size_t)lt * a.nsg + sg) * E123;
@@ -653,6 +661,248 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
   for (int i = 0; i < kMaxOwned; ++i) {
     const int x = tid + i * kThreads;
     if (x >= E123) break;
+    dst[x] = tacc[i];
+  }
+}
+
+// =====================================================================================
+// adjoint for large kernels (kp >= 512): the same contraction and col2im, tiled for
+// operand reuse. A workgroup computes H^T for 128 tile rows x 256 kernel offsets over
+// all eigendirections; chunks of 16 eigendirections of G (formed from U, Q, s) and of
+// V are staged cooperatively in LDS (double buffered) and each wavefront computes
+// 64 rows x 128 offsets (eight 32x32 accumulators), so every G element is fetched once
+// per workgroup and every V element once per workgroup. The col2im then runs in two
+// rounds of 128 offsets through the shared gather.
+// =====================================================================================
+constexpr int kBigChunk = 16;            // eigendirections per staged chunk
+constexpr int kBigPad = kBigChunk + 1;   // LDS row stride (odd: conflict-free columns)
+
+__global__ __launch_bounds__(kThreads, 2) void k_adjoint_big(StageArgs a) {
+  extern __shared__ float smem[];
+  const int2 tt = a.tiles[blockIdx.x];
+  const InstDev& I = a.inst[tt.x];
+  if (I.st->phase != kRun || !runs_iteration<kFP32>(I, I.st)) return;
+  const int kp = a.kp, k = a.k;
+  const int sg = blockIdx.y;
+  const int lt = tt.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5;
+  const int nkb = kp / 32;
+  const int rw = wave & 1, sh = wave >> 1;             // row chunk, offset half
+  float* Gs = smem;                                    // [2][128][kBigPad]
+  float* Vs = smem + 2 * 128 * kBigPad;                // [2][256][kBigPad]
+  float tacc[kMaxOwned];
+#pragma unroll
+  for (int i = 0; i < kMaxOwned; ++i) tacc[i] = 0.f;
+
+  floatx16 acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (floatx16)(0.0f);
+
+  // cooperative share of a chunk: thread t stages G for (row group t/64, lane t%64)
+  // of the tile layout (8 values) and V row s = t of this offset group (16 values)
+  gcfloat4* U4 = gc4(I.U);
+  gcfloat4* Q4 = gc4(I.Q);
+  const int rg = tid >> 6, hf = (tid >> 5) & 1;
+  const float* vrow = a.Vp + (size_t)(sg * kGroup + tid) * kp;
+  float4 cu[2], cq[2], cs[2], cv[4];
+  auto coop_load = [&](int q) {
+    const int cb = q >> 1, p = q & 1;
+    const size_t o = (((size_t)lt * 4 + rg) * nkb + cb) * 256 + lane * 4 + 2 * p;
+    cu[0] = U4[o];
+    cu[1] = U4[o + 1];
+    cq[0] = Q4[o];
+    cq[1] = Q4[o + 1];
+    cs[0] = *gc4(I.s + cb * 32 + (2 * p) * 8 + hf * 4);
+    cs[1] = *gc4(I.s + cb * 32 + (2 * p + 1) * 8 + hf * 4);
+    gcfloat4* vp = gc4(vrow + q * kBigChunk);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cv[i] = vp[i];
+  };
+  auto coop_store = [&](int buf) {
+    // G values of v = 8p..8p+7 sit at chunk columns (v%8/4)*8 + hf*4 + v%4
+    float* gd = Gs + ((size_t)buf * 128 + rg * 32 + (lane & 31)) * kBigPad + hf * 4;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      gd[8 * t + 0] = cu[t].x + cs[t].x * cq[t].x;
+      gd[8 * t + 1] = cu[t].y + cs[t].y * cq[t].y;
+      gd[8 * t + 2] = cu[t].z + cs[t].z * cq[t].z;
+      gd[8 * t + 3] = cu[t].w + cs[t].w * cq[t].w;
+    }
+    float* vd = Vs + ((size_t)buf * 256 + tid) * kBigPad;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      vd[4 * i + 0] = cv[i].x;
+      vd[4 * i + 1] = cv[i].y;
+      vd[4 * i + 2] = cv[i].z;
+      vd[4 * i + 3] = cv[i].w;
+    }
+  };
+  const int nq = kp / kBigChunk;
+  coop_load(0);
+  coop_store(0);
+  __syncthreads();
+  for (int q = 0; q < nq; ++q) {
+    const int buf = q & 1;
+    if (q + 1 < nq) coop_load(q + 1);
+    const float* gb = Gs + ((size_t)buf * 128 + rw * 64 + (lane & 31)) * kBigPad + half;
+    const float* vb = Vs + ((size_t)buf * 256 + sh * 128 + (lane & 31)) * kBigPad + half;
+#pragma unroll
+    for (int kk = 0; kk < kBigChunk / 2; ++kk) {
+      const float g0 = gb[2 * kk], g1 = gb[32 * kBigPad + 2 * kk];
+      float v[4];
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb) v[sb] = vb[sb * 32 * kBigPad + 2 * kk];
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb) {
+        acc[sb][0] = mfma32(v[sb], g0, acc[sb][0]);
+        acc[sb][1] = mfma32(v[sb], g1, acc[sb][1]);
+      }
+    }
+    if (q + 1 < nq) coop_store(buf ^ 1);
+    __syncthreads();
+  }
+  // col2im in two rounds of 128 offsets: the wavefronts of offset half `rd` stage
+  const int hstride = 128 + 4;
+  float* Hs = smem;
+  for (int rd = 0; rd < 2; ++rd) {
+    const int S0 = sg * kGroup + rd * 128;
+    if (sh == rd) {
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+          for (int v = 0; v < 16; ++v)
+            Hs[(sb * 32 + acc_col(v, half)) * hstride + rw * 64 + jb * 32 + (lane & 31)] = acc[sb][jb][v];
+    }
+    __syncthreads();
+    gather_round(I, Hs, hstride, S0, min(S0 + 128, k), tacc);
+    __syncthreads();
+  }
+  float* dst = I.part + ((size_t)lt * a.nsg + sg) * I.E123;
+#pragma unroll
+  for (int i = 0; i < kMaxOwned; ++i) {
+    const int x = tid + i * kThreads;
+    if (x >= I.E123) break;
+    dst[x] = tacc[i];
+  }
+}
+
+// Reduced-precision variant of the tiled large-kernel adjoint: chunks of 32
+// eigendirections, dG = (s - 1) Q - U / ratio_prev and V converted to BF16/FP16 when
+// staged, 32x32x16 MFMA (two k-steps per chunk), FP32 accumulation.
+constexpr int kBigLpChunk = 32;
+constexpr int kBigLpPad = kBigLpChunk + 8;  // halves per LDS row (16-byte aligned rows)
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
+  typedef typename LowP<MODE>::h H;
+  typedef typename LowP<MODE>::v8 V8;
+  extern __shared__ float smem[];
+  const int2 tt = a.tiles[blockIdx.x];
+  const InstDev& I = a.inst[tt.x];
+  if (I.st->phase != kRun || !runs_iteration<MODE>(I, I.st)) return;
+  const int kp = a.kp, k = a.k;
+  const int sg = blockIdx.y;
+  const int lt = tt.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5;
+  const int nkb = kp / 32;
+  const int rw = wave & 1, sh = wave >> 1;
+  H* Gs = reinterpret_cast<H*>(smem);                  // [2][128][kBigLpPad]
+  H* Vs = Gs + 2 * 128 * kBigLpPad;                    // [2][256][kBigLpPad]
+  float tacc[kMaxOwned];
+#pragma unroll
+  for (int i = 0; i < kMaxOwned; ++i) tacc[i] = 0.f;
+  floatx16 acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (floatx16)(0.0f);
+
+  gcfloat4* U4 = gc4(I.U);
+  gcfloat4* Q4 = gc4(I.Q);
+  const float rp = (float)(1.0 / I.st->ratio_prev);
+  const int rg = tid >> 6, hf = (tid >> 5) & 1;
+  const float* vrow = a.Vp + (size_t)(sg * kGroup + tid) * kp;
+  float4 cu[4], cq[4], cs[4], cv[8];
+  auto coop_load = [&](int cb) {
+    const size_t o = (((size_t)lt * 4 + rg) * nkb + cb) * 256 + lane * 4;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      cu[g] = U4[o + g];
+      cq[g] = Q4[o + g];
+      cs[g] = *gc4(I.s + cb * 32 + g * 8 + hf * 4);
+    }
+    gcfloat4* vp = gc4(vrow + cb * 32);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) cv[i] = vp[i];
+  };
+  auto coop_store = [&](int buf) {
+    H* gd = Gs + ((size_t)buf * 128 + rg * 32 + (lane & 31)) * kBigLpPad + hf * 4;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {  // value v = 4g + e sits at column acc_col(v, hf) = 8g + 4hf + e
+      gd[8 * g + 0] = (H)((cs[g].x - 1.f) * cq[g].x - cu[g].x * rp);
+      gd[8 * g + 1] = (H)((cs[g].y - 1.f) * cq[g].y - cu[g].y * rp);
+      gd[8 * g + 2] = (H)((cs[g].z - 1.f) * cq[g].z - cu[g].z * rp);
+      gd[8 * g + 3] = (H)((cs[g].w - 1.f) * cq[g].w - cu[g].w * rp);
+    }
+    H* vd = Vs + ((size_t)buf * 256 + tid) * kBigLpPad;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      vd[4 * i + 0] = (H)cv[i].x;
+      vd[4 * i + 1] = (H)cv[i].y;
+      vd[4 * i + 2] = (H)cv[i].z;
+      vd[4 * i + 3] = (H)cv[i].w;
+    }
+  };
+  coop_load(0);
+  coop_store(0);
+  __syncthreads();
+  for (int q = 0; q < nkb; ++q) {
+    const int buf = q & 1;
+    if (q + 1 < nkb) coop_load(q + 1);
+    const H* gb = Gs + ((size_t)buf * 128 + rw * 64 + (lane & 31)) * kBigLpPad + 8 * half;
+    const H* vb = Vs + ((size_t)buf * 256 + sh * 128 + (lane & 31)) * kBigLpPad + 8 * half;
+#pragma unroll
+    for (int kk = 0; kk < kBigLpChunk / 16; ++kk) {
+      V8 g0, g1, v[4];
+      __builtin_memcpy(&g0, gb + 16 * kk, 16);
+      __builtin_memcpy(&g1, gb + 32 * kBigLpPad + 16 * kk, 16);
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb) __builtin_memcpy(&v[sb], vb + sb * 32 * kBigLpPad + 16 * kk, 16);
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb) {
+        acc[sb][0] = LowP<MODE>::mfma(v[sb], g0, acc[sb][0]);
+        acc[sb][1] = LowP<MODE>::mfma(v[sb], g1, acc[sb][1]);
+      }
+    }
+    if (q + 1 < nkb) coop_store(buf ^ 1);
+    __syncthreads();
+  }
+  const int hstride = 128 + 4;
+  float* Hs = smem;
+  for (int rd = 0; rd < 2; ++rd) {
+    const int S0 = sg * kGroup + rd * 128;
+    if (sh == rd) {
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+          for (int v = 0; v < 16; ++v)
+            Hs[(sb * 32 + acc_col(v, half)) * hstride + rw * 64 + jb * 32 + (lane & 31)] = acc[sb][jb][v];
+    }
+    __syncthreads();
+    gather_round(I, Hs, hstride, S0, min(S0 + 128, k), tacc);
+    __syncthreads();
+  }
+  float* dst = I.part + ((size_t)lt * a.nsg + sg) * I.E123;
+#pragma unroll
+  for (int i = 0; i < kMaxOwned; ++i) {
+    const int x = tid + i * kThreads;
+    if (x >= I.E123) break;
     dst[x] = tacc[i];
   }
 }
@@ -908,10 +1158,14 @@ __global__ __launch_bounds__(kThreads) void k_colnorm_finish(StageArgs a) {
 //   Vf[((cb * nkb + sb) * 64 + l) * 16 + j] = V[sb*32 + 2j + l/32][cb*32 + l%32]
 //   Va[((sb * nkb + cb) * 64 + l) * 16 + v] = V[sb*32 + l%32][cb*32 + acc_col(v, l/32)]
 // =====================================================================================
-__global__ void k_prep_v(const float* V, int k, int kp, float* Vf, float* Va) {
+__global__ void k_prep_v(const float* V, int k, int kp, float* Vf, float* Va, float* Vp) {
   const int nkb = kp / 32;
   const int64_t n = (int64_t)kp * kp;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    {  // plain zero-padded kp x kp
+      const int s = (int)(e / kp), c = (int)(e % kp);
+      Vp[e] = (s < k && c < k) ? V[(int64_t)s * k + c] : 0.f;
+    }
     const int j = (int)(e & 15);
     const int l = (int)((e >> 4) & 63);
     const int64_t blk = e >> 10;
@@ -1039,6 +1293,18 @@ void launch_colnorm(const StageArgs& a, int nslices_total, int ninst, hipStream_
   hipLaunchKernelGGL(k_colnorm_finish, dim3(ninst), dim3(kThreads), 0, st, a);
 }
 
+void launch_adjoint_big(const StageArgs& a, int ntiles_total, int mode, hipStream_t st) {
+  const dim3 g(ntiles_total, a.nsg), b(kThreads);
+  if (mode == kFP32) {
+    const int lds = std::max(2 * (128 + 256) * kBigPad, 128 * (128 + 4));
+    hipLaunchKernelGGL(k_adjoint_big, g, b, lds * 4, st, a);
+  } else {
+    const int lds = std::max((2 * (128 + 256) * kBigLpPad + 1) / 2, 128 * (128 + 4));
+    if (mode == kBF16) hipLaunchKernelGGL(k_adjoint_big_lp<kBF16>, g, b, lds * 4, st, a);
+    if (mode == kFP16) hipLaunchKernelGGL(k_adjoint_big_lp<kFP16>, g, b, lds * 4, st, a);
+  }
+}
+
 void launch_adjoint(const StageArgs& a, int ntiles_total, int lds_floats, int mode, hipStream_t st) {
   const dim3 g(ntiles_total, a.nsg), b(kThreads);
   if (mode == kBF16)
@@ -1063,10 +1329,10 @@ void launch_forward(const StageArgs& a, int ntiles_total, int lds_floats, int mo
     hipLaunchKernelGGL(k_forward<kFP32>, g, b, lds_floats * 4, st, a);
 }
 
-void launch_prep_v(const float* V, int k, int kp, float* Vf, float* Va, void* Vf_lo, void* Va_lo, int prec,
-                   hipStream_t st) {
+void launch_prep_v(const float* V, int k, int kp, float* Vf, float* Va, float* Vp, void* Vf_lo, void* Va_lo,
+                   int prec, hipStream_t st) {
   const dim3 g(grid_for((int64_t)kp * kp, 4096)), b(kThreads);
-  hipLaunchKernelGGL(k_prep_v, g, b, 0, st, V, k, kp, Vf, Va);
+  hipLaunchKernelGGL(k_prep_v, g, b, 0, st, V, k, kp, Vf, Va, Vp);
   if (prec == kBF16) hipLaunchKernelGGL(k_prep_v_lp<kBF16>, g, b, 0, st, V, k, kp, Vf_lo, Va_lo);
   if (prec == kFP16) hipLaunchKernelGGL(k_prep_v_lp<kFP16>, g, b, 0, st, V, k, kp, Vf_lo, Va_lo);
 }

@@ -136,6 +136,7 @@ static Plan make_plan(const int m[3], const int k[3], int kp) {
   int force[3] = {0, 0, 0};
   if (const char* e = getenv("ICNNM_TILE")) sscanf(e, "%d,%d,%d", &force[0], &force[1], &force[2]);
   for (int bm : {64, 128, 256, 512}) {
+    if (kp >= 512 && bm != 128) continue;  // the tiled large-kernel adjoint uses 128-row tiles
     for (int b2 = 1; b2 <= bm; b2 <<= 1) {
       if (b2 > pow2ceil(m[2]) && b2 * pow2ceil(m[1]) * pow2ceil(m[0]) > bm) continue;
       for (int b1 = 1; b1 * b2 <= bm && b1 <= pow2ceil(m[1]); b1 <<= 1) {
@@ -258,7 +259,8 @@ struct Group {
   int kd[3];
   int k, kp, nsg, ncg, prec;
   const float* Vsrc = nullptr;
-  DevBuf Vf, Va, Vlo_f, Vlo_a;
+  DevBuf Vf, Va, Vp, Vlo_f, Vlo_a;
+  bool big = false;  // kp >= 512: 128-row tiles and the tiled adjoint
   std::vector<Member*> members;
   int capacity;
   DevBuf states;  // InstState[capacity]
@@ -298,11 +300,12 @@ struct Group {
     const size_t n = (size_t)kp * kp;
     Vf.ensure(budget, n * 4);
     Va.ensure(budget, n * 4);
+    Vp.ensure(budget, n * 4);
     if (prec != kFP32) {
       Vlo_f.ensure(budget, n * 2);
       Vlo_a.ensure(budget, n * 2);
     }
-    launch_prep_v(V, k, kp, Vf.as<float>(), Va.as<float>(), Vlo_f.p, Vlo_a.p, prec, st);
+    launch_prep_v(V, k, kp, Vf.as<float>(), Va.as<float>(), Vp.as<float>(), Vlo_f.p, Vlo_a.p, prec, st);
     HIPCK(hipGetLastError());
   }
 
@@ -429,6 +432,7 @@ struct Group {
     a.slices = slices.as<int2>();
     a.Vf = Vf.as<float>();
     a.Va = Va.as<float>();
+    a.Vp = Vp.as<float>();
     a.Vf_lo = Vlo_f.p;
     a.Va_lo = Vlo_a.p;
     a.kp = kp;
@@ -443,8 +447,13 @@ struct Group {
   void launch_round(hipStream_t st) {
     const StageArgs a = args();
     launch_colnorm(a, nslice_total, (int)members.size(), st);
-    launch_adjoint(a, ntiles_total, lds_adj, kFP32, st);
-    if (prec != kFP32) launch_adjoint(a, ntiles_total, lds_adj, prec, st);
+    if (kp >= 512) {
+      launch_adjoint_big(a, ntiles_total, kFP32, st);
+      if (prec != kFP32) launch_adjoint_big(a, ntiles_total, prec, st);
+    } else {
+      launch_adjoint(a, ntiles_total, lds_adj, kFP32, st);
+      if (prec != kFP32) launch_adjoint(a, ntiles_total, lds_adj, prec, st);
+    }
     launch_lstep(a, nlblk_total, st);
     launch_forward(a, ntiles_total, lds_fwd, kFP32, st);
     if (prec != kFP32) launch_forward(a, ntiles_total, lds_fwd, prec, st);
@@ -461,8 +470,13 @@ struct Group {
     launch_colnorm(a, nslice_total, (int)members.size(), st);
     HIPCK(hipEventRecord(prof->ev[1], st));
     HIPCK(hipEventRecord(prof->ev[2], st));
-    launch_adjoint(a, ntiles_total, lds_adj, kFP32, st);
-    if (prec != kFP32) launch_adjoint(a, ntiles_total, lds_adj, prec, st);
+    if (kp >= 512) {
+      launch_adjoint_big(a, ntiles_total, kFP32, st);
+      if (prec != kFP32) launch_adjoint_big(a, ntiles_total, prec, st);
+    } else {
+      launch_adjoint(a, ntiles_total, lds_adj, kFP32, st);
+      if (prec != kFP32) launch_adjoint(a, ntiles_total, lds_adj, prec, st);
+    }
     HIPCK(hipEventRecord(prof->ev[3], st));
     HIPCK(hipEventRecord(prof->ev[4], st));
     launch_lstep(a, nlblk_total, st);

@@ -34,7 +34,8 @@ def _case(dims, kdims, pm, seed, b=6):
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 @pytest.mark.parametrize("dims,kdims,seed", [((16, 16, 8), (4, 4, 4), 1), ((24, 20, 16), (5, 3, 8), 2),
-                                             ((9, 33), (3, 4), 3)])
+                                             ((9, 33), (3, 4), 3), ((24, 24, 8), (8, 8, 8), 4),
+                                             ((16, 16, 16), (16, 16, 4), 5)])
 def test_reduced_precision_parity(lib, prec, dims, kdims, seed):
     prob, V32 = _case(dims, kdims, 0.4, seed)
     iters = 60

@@ -50,6 +50,9 @@ CASES = [
     ((9, 33), (4, 5), 0.5, 4),             # order 2
     ((70,), (9,), 0.4, 5),                 # order 1
     ((24, 20, 16), (5, 5, 4), 0.35, 6),    # k = 100, several tiles per dimension
+    ((24, 24, 8), (8, 8, 8), 0.4, 7),      # k = 512: the tiled large-kernel adjoint
+    ((20, 18, 12), (6, 6, 9), 0.4, 8),     # k = 324 padded to 512, ragged tiles
+    ((16, 16, 16), (16, 16, 4), 0.5, 9),   # k = 1024, the 16x16x4 kernel
 ]
 
 

@@ -80,7 +80,9 @@ struct StageArgs {
   const float* Vp;       // V zero-padded to kp x kp, row-major (FP32)
   const void* Vf_lo;     // forward operand layout of V (BF16/FP16)
   const void* Va_lo;     // adjoint operand layout of V (BF16/FP16)
+  const void* Vp_lo;     // V zero-padded to kp x kp, row-major (BF16/FP16)
   int32_t kp, k, nsg, ncg;
+  int32_t ntiles;        // entries of `tiles`
   int32_t tiles_per_slice;
   int32_t prec;
 };
@@ -88,14 +90,16 @@ struct StageArgs {
 // Launchers (defined in kernels.hip). All take the stream to launch on.
 void launch_colnorm(const StageArgs& a, int nslices_total, int ninst, hipStream_t st);
 // mode 0: FP32 contraction (initialisation, FP32 solves, refresh iterations);
-// mode 1 / 2: BF16 / FP16 contraction of the change since the previous iteration
-void launch_adjoint(const StageArgs& a, int ntiles_total, int lds_floats, int mode, hipStream_t st);
+// mode 1 / 2: BF16 / FP16 contraction of the change since the previous iteration.
+// gv: col2im gather variant, 0 generic, 8 box lines (innermost kernel extent 4,
+// innermost tile extent 8, E0 E1 <= 512 for every instance of the launch)
+void launch_adjoint(const StageArgs& a, int ntiles_total, int lds_floats, int mode, int gv, hipStream_t st);
 void launch_lstep(const StageArgs& a, int nlblocks_total, hipStream_t st);
 void launch_forward(const StageArgs& a, int ntiles_total, int lds_floats, int mode, hipStream_t st);
 void launch_prep_v(const float* V, int k, int kp, float* Vf, float* Va, float* Vp, void* Vf_lo,
-                   void* Va_lo, int prec, hipStream_t st);
+                   void* Va_lo, void* Vp_lo, int prec, hipStream_t st);
 // adjoint tiled for large kernels (kp >= 512, 128-row tiles)
-void launch_adjoint_big(const StageArgs& a, int ntiles_total, int mode, hipStream_t st);
+void launch_adjoint_big(const StageArgs& a, int ntiles_total, int mode, int gv, hipStream_t st);
 void launch_check_v(const float* V, int k, float* out_maxdev, hipStream_t st);
 void launch_autocorr(const float* L, const int32_t* m, const int32_t* k, double* R,
                      hipStream_t st);

@@ -500,14 +500,123 @@ __device__ __forceinline__ void gather_round(const InstDev& I, const float* Hs, 
   }
 }
 
-template <int MODE>
+// Adjoint workgroup -> (global tile, offset group). Workgroup w runs on XCD w % 8; the
+// nsg workgroups of one tile are placed consecutively on one XCD so that the tile's U
+// and Q rows, read by each of them, come from HBM once and from that XCD's L2 after.
+// The grid holds 8 * ceil(ntiles / 8) * nsg workgroups; the padding ones exit.
+__device__ __forceinline__ bool adjoint_item(const StageArgs& a, int2& tt, int& sg) {
+  const int w = blockIdx.x, n = w >> 3;
+  sg = n % a.nsg;
+  const int tile = (n / a.nsg) * 8 + (w & 7);
+  if (tile >= a.ntiles) return false;
+  tt = a.tiles[tile];
+  return true;
+}
+
+// col2im gather specialised for an innermost kernel extent of 4 and an innermost
+// tile extent of B2 rows: a thread owns whole box lines (x0, x1) and keeps all
+// E2 = B2 + 3 positions of each line in registers. For every kernel pair (p, q) of
+// the round whose rows (j0, j1) lie in the tile, the 4 x B2 block
+// H[(j0, j1, j2)][(p, q, r)] (contiguous in j2, read as float4) is added along its
+// anti-diagonals x2 = j2 + 3 - r. Every position receives its terms in the same
+// (p, q, r) order as gather_round, so both give identical sums.
+template <int B2, int LMAX>
+__device__ __forceinline__ void gather_lines(const InstDev& I, const float* Hs, int hstride, int S0, int S1,
+                                             float (&lacc)[LMAX][B2 + 3]) {
+  const int k0 = I.k[0], k1 = I.k[1];
+  const int E1 = I.E[1], nl = I.E[0] * E1;
+  const int b0 = I.b[0], b1 = I.b[1];
+  const int pq0 = S0 >> 2, pq1 = S1 >> 2;  // kernel pairs (p, q) staged this round
+#pragma unroll
+  for (int li = 0; li < LMAX; ++li) {
+    const int l = threadIdx.x + li * kThreads;
+    if (l >= nl) break;
+    const int x0 = l / E1, x1 = l - x0 * E1;
+    const int lo0 = max(0, k0 - 1 - x0), hi0 = min(k0, k0 - 1 - x0 + b0);
+    const int lo1 = max(0, k1 - 1 - x1), hi1 = min(k1, k1 - 1 - x1 + b1);
+    for (int p = max(lo0, pq0 / k1); p < hi0 && p * k1 < pq1; ++p) {
+      const int j0 = x0 - (k0 - 1) + p;
+      const int qa = max(lo1, pq0 - p * k1), qb = min(hi1, pq1 - p * k1);
+      for (int q = qa; q < qb; ++q) {
+        const int j1 = x1 - (k1 - 1) + q;
+        const float* h = Hs + ((p * k1 + q) * 4 - S0) * hstride + (j0 * b1 + j1) * B2;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+          for (int j = 0; j < B2; j += 4) {
+            const float4 v = *reinterpret_cast<const float4*>(h + r * hstride + j);
+            lacc[li][j + 3 - r] += v.x;
+            lacc[li][j + 4 - r] += v.y;
+            lacc[li][j + 5 - r] += v.z;
+            lacc[li][j + 6 - r] += v.w;
+          }
+        }
+      }
+    }
+  }
+}
+
+// Per-thread col2im accumulators of one adjoint workgroup. GV = 0: box positions
+// (any geometry, E123 <= 4096); GV = 8: box lines for an innermost kernel extent of 4
+// and tile rows of 8 along the innermost dimension (at most 512 lines). The host picks
+// GV per launch from the plans of the instances it covers.
+template <int GV>
+struct GatherAcc;
+
+template <>
+struct GatherAcc<0> {
+  float t[kMaxOwned];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int i = 0; i < kMaxOwned; ++i) t[i] = 0.f;
+  }
+  __device__ __forceinline__ void round(const InstDev& I, const float* Hs, int hstride, int S0, int S1) {
+    gather_round(I, Hs, hstride, S0, S1, t);
+  }
+  __device__ __forceinline__ void store(const InstDev& I, float* dst) const {
+#pragma unroll
+    for (int i = 0; i < kMaxOwned; ++i) {
+      const int x = threadIdx.x + i * kThreads;
+      if (x >= I.E123) break;
+      dst[x] = t[i];
+    }
+  }
+};
+
+template <>
+struct GatherAcc<8> {
+  static constexpr int kLines = 2, kE2 = 8 + 3;
+  float t[kLines][kE2];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int i = 0; i < kLines; ++i)
+#pragma unroll
+      for (int j = 0; j < kE2; ++j) t[i][j] = 0.f;
+  }
+  __device__ __forceinline__ void round(const InstDev& I, const float* Hs, int hstride, int S0, int S1) {
+    gather_lines<8, kLines>(I, Hs, hstride, S0, S1, t);
+  }
+  __device__ __forceinline__ void store(const InstDev& I, float* dst) const {
+    const int nl = I.E[0] * I.E[1];
+#pragma unroll
+    for (int i = 0; i < kLines; ++i) {
+      const int l = threadIdx.x + i * kThreads;
+      if (l >= nl) break;
+#pragma unroll
+      for (int j = 0; j < kE2; ++j) dst[l * kE2 + j] = t[i][j];
+    }
+  }
+};
+
+template <int MODE, int GV>
 __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
   extern __shared__ float smem[];
-  const int2 tt = a.tiles[blockIdx.x];
+  int2 tt;
+  int sg;
+  if (!adjoint_item(a, tt, sg)) return;
   const InstDev& I = a.inst[tt.x];
   if (I.st->phase != kRun || !runs_iteration<MODE>(I, I.st)) return;
   const int kp = a.kp, k = a.k;
-  const int sg = blockIdx.y;
   const int SGW = kp < kGroup ? kp : kGroup;
   const int lt = tt.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5;
@@ -521,9 +630,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
 
   // owned box positions and their valid kernel-offset ranges per dimension
   const int E123 = I.E123;
-  float tacc[kMaxOwned];
-#pragma unroll
-  for (int i = 0; i < kMaxOwned; ++i) tacc[i] = 0.f;
+  GatherAcc<GV> gacc;
+  gacc.zero();
 
   const int nkb = kp / 32;
   const int nhb = 2 * nkb;  // half column blocks of 8 MFMA k-steps
@@ -653,16 +761,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
         }
     }
     __syncthreads();
-    gather_round(I, Hs, hstride, S0, min(S0 + spr, k), tacc);
+    gacc.round(I, Hs, hstride, S0, min(S0 + spr, k));
     __syncthreads();
   }
-  float* dst = I.part + ((size_t)lt * a.nsg + sg) * E123;
-#pragma unroll
-  for (int i = 0; i < kMaxOwned; ++i) {
-    const int x = tid + i * kThreads;
-    if (x >= E123) break;
-    dst[x] = tacc[i];
-  }
+  gacc.store(I, I.part + ((size_t)lt * a.nsg + sg) * E123);
 }
 
 // =====================================================================================
@@ -677,22 +779,23 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
 constexpr int kBigChunk = 16;            // eigendirections per staged chunk
 constexpr int kBigPad = kBigChunk + 1;   // LDS row stride (odd: conflict-free columns)
 
+template <int GV>
 __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big(StageArgs a) {
   extern __shared__ float smem[];
-  const int2 tt = a.tiles[blockIdx.x];
+  int2 tt;
+  int sg;
+  if (!adjoint_item(a, tt, sg)) return;
   const InstDev& I = a.inst[tt.x];
   if (I.st->phase != kRun || !runs_iteration<kFP32>(I, I.st)) return;
   const int kp = a.kp, k = a.k;
-  const int sg = blockIdx.y;
   const int lt = tt.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5;
   const int nkb = kp / 32;
   const int rw = wave & 1, sh = wave >> 1;             // row chunk, offset half
   float* Gs = smem;                                    // [2][128][kBigPad]
   float* Vs = smem + 2 * 128 * kBigPad;                // [2][256][kBigPad]
-  float tacc[kMaxOwned];
-#pragma unroll
-  for (int i = 0; i < kMaxOwned; ++i) tacc[i] = 0.f;
+  GatherAcc<GV> gacc;
+  gacc.zero();
 
   floatx16 acc[4][2];
 #pragma unroll
@@ -778,43 +881,45 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big(StageArgs a) {
             Hs[(sb * 32 + acc_col(v, half)) * hstride + rw * 64 + jb * 32 + (lane & 31)] = acc[sb][jb][v];
     }
     __syncthreads();
-    gather_round(I, Hs, hstride, S0, min(S0 + 128, k), tacc);
+    gacc.round(I, Hs, hstride, S0, min(S0 + 128, k));
     __syncthreads();
   }
-  float* dst = I.part + ((size_t)lt * a.nsg + sg) * I.E123;
-#pragma unroll
-  for (int i = 0; i < kMaxOwned; ++i) {
-    const int x = tid + i * kThreads;
-    if (x >= I.E123) break;
-    dst[x] = tacc[i];
-  }
+  gacc.store(I, I.part + ((size_t)lt * a.nsg + sg) * I.E123);
 }
 
 // Reduced-precision variant of the tiled large-kernel adjoint: chunks of 32
-// eigendirections, dG = (s - 1) Q - U / ratio_prev and V converted to BF16/FP16 when
-// staged, 32x32x16 MFMA (two k-steps per chunk), FP32 accumulation.
+// eigendirections, dG = (s - 1) Q - U / ratio_prev converted to BF16/FP16 when
+// staged, V read from its zero-padded BF16/FP16 copy, 32x32x16 MFMA (two k-steps per
+// chunk) with FP32 accumulation. LDS rows are 40 halves (80 bytes): 16-byte vector
+// reads of eight consecutive rows then fall on distinct banks.
 constexpr int kBigLpChunk = 32;
-constexpr int kBigLpPad = kBigLpChunk + 8;  // halves per LDS row (16-byte aligned rows)
+constexpr int kBigLpPad = kBigLpChunk + 8;
+// floats of LDS before the shrink factors: the staging buffers or the staged H^T
+constexpr int kBigLpStage = (2 * (128 + 256) * kBigLpPad / 2 > 128 * (128 + 4)) ? 2 * (128 + 256) * kBigLpPad / 2
+                                                                                  : 128 * (128 + 4);
 
-template <int MODE>
+template <int MODE, int GV>
 __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
   typedef typename LowP<MODE>::h H;
   typedef typename LowP<MODE>::v8 V8;
+  typedef typename LowP<MODE>::v4 V4;
   extern __shared__ float smem[];
-  const int2 tt = a.tiles[blockIdx.x];
+  int2 tt;
+  int sg;
+  if (!adjoint_item(a, tt, sg)) return;
   const InstDev& I = a.inst[tt.x];
   if (I.st->phase != kRun || !runs_iteration<MODE>(I, I.st)) return;
   const int kp = a.kp, k = a.k;
-  const int sg = blockIdx.y;
   const int lt = tt.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5;
   const int nkb = kp / 32;
   const int rw = wave & 1, sh = wave >> 1;
   H* Gs = reinterpret_cast<H*>(smem);                  // [2][128][kBigLpPad]
   H* Vs = Gs + 2 * 128 * kBigLpPad;                    // [2][256][kBigLpPad]
-  float tacc[kMaxOwned];
-#pragma unroll
-  for (int i = 0; i < kMaxOwned; ++i) tacc[i] = 0.f;
+  float* Ss = smem + kBigLpStage;                      // shrink factors [kp]
+  for (int c = threadIdx.x; c < kp; c += kThreads) Ss[c] = I.s[c];
+  GatherAcc<GV> gacc;
+  gacc.zero();
   floatx16 acc[4][2];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -825,40 +930,44 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
   gcfloat4* Q4 = gc4(I.Q);
   const float rp = (float)(1.0 / I.st->ratio_prev);
   const int rg = tid >> 6, hf = (tid >> 5) & 1;
-  const float* vrow = a.Vp + (size_t)(sg * kGroup + tid) * kp;
-  float4 cu[4], cq[4], cs[4], cv[8];
+  // thread t stages G of (row group t/64, lane t%64) of the tile layout (16 values)
+  // and the 32 halves of V row s = t of this offset group
+  gcfloat4* vrow = gc4(a.Vp_lo) + (size_t)(sg * kGroup + tid) * (kp / 8);
+  float4 cu[4], cq[4], cv0, cv1, cv2, cv3;
   auto coop_load = [&](int cb) {
     const size_t o = (((size_t)lt * 4 + rg) * nkb + cb) * 256 + lane * 4;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       cu[g] = U4[o + g];
       cq[g] = Q4[o + g];
-      cs[g] = *gc4(I.s + cb * 32 + g * 8 + hf * 4);
     }
-    gcfloat4* vp = gc4(vrow + cb * 32);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) cv[i] = vp[i];
+    cv0 = vrow[cb * 4 + 0];
+    cv1 = vrow[cb * 4 + 1];
+    cv2 = vrow[cb * 4 + 2];
+    cv3 = vrow[cb * 4 + 3];
   };
-  auto coop_store = [&](int buf) {
+  auto coop_store = [&](int buf, int cb) {
+    // value v = 4g + e of the tile layout sits at column acc_col(v, hf) = 8g + 4hf + e
     H* gd = Gs + ((size_t)buf * 128 + rg * 32 + (lane & 31)) * kBigLpPad + hf * 4;
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {  // value v = 4g + e sits at column acc_col(v, hf) = 8g + 4hf + e
-      gd[8 * g + 0] = (H)((cs[g].x - 1.f) * cq[g].x - cu[g].x * rp);
-      gd[8 * g + 1] = (H)((cs[g].y - 1.f) * cq[g].y - cu[g].y * rp);
-      gd[8 * g + 2] = (H)((cs[g].z - 1.f) * cq[g].z - cu[g].z * rp);
-      gd[8 * g + 3] = (H)((cs[g].w - 1.f) * cq[g].w - cu[g].w * rp);
+    for (int g = 0; g < 4; ++g) {
+      const float4 sv = *reinterpret_cast<const float4*>(Ss + cb * 32 + g * 8 + hf * 4);
+      V4 t;
+      t[0] = (H)((sv.x - 1.f) * cq[g].x - cu[g].x * rp);
+      t[1] = (H)((sv.y - 1.f) * cq[g].y - cu[g].y * rp);
+      t[2] = (H)((sv.z - 1.f) * cq[g].z - cu[g].z * rp);
+      t[3] = (H)((sv.w - 1.f) * cq[g].w - cu[g].w * rp);
+      *reinterpret_cast<V4*>(gd + 8 * g) = t;
     }
-    H* vd = Vs + ((size_t)buf * 256 + tid) * kBigLpPad;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      vd[4 * i + 0] = (H)cv[i].x;
-      vd[4 * i + 1] = (H)cv[i].y;
-      vd[4 * i + 2] = (H)cv[i].z;
-      vd[4 * i + 3] = (H)cv[i].w;
-    }
+    float4* vd = reinterpret_cast<float4*>(Vs + ((size_t)buf * 256 + tid) * kBigLpPad);
+    vd[0] = cv0;
+    vd[1] = cv1;
+    vd[2] = cv2;
+    vd[3] = cv3;
   };
   coop_load(0);
-  coop_store(0);
+  __syncthreads();
+  coop_store(0, 0);
   __syncthreads();
   for (int q = 0; q < nkb; ++q) {
     const int buf = q & 1;
@@ -867,18 +976,18 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
     const H* vb = Vs + ((size_t)buf * 256 + sh * 128 + (lane & 31)) * kBigLpPad + 8 * half;
 #pragma unroll
     for (int kk = 0; kk < kBigLpChunk / 16; ++kk) {
-      V8 g0, g1, v[4];
-      __builtin_memcpy(&g0, gb + 16 * kk, 16);
-      __builtin_memcpy(&g1, gb + 32 * kBigLpPad + 16 * kk, 16);
+      const V8 g0 = *reinterpret_cast<const V8*>(gb + 16 * kk);
+      const V8 g1 = *reinterpret_cast<const V8*>(gb + 32 * kBigLpPad + 16 * kk);
+      V8 v[4];
 #pragma unroll
-      for (int sb = 0; sb < 4; ++sb) __builtin_memcpy(&v[sb], vb + sb * 32 * kBigLpPad + 16 * kk, 16);
+      for (int sb = 0; sb < 4; ++sb) v[sb] = *reinterpret_cast<const V8*>(vb + sb * 32 * kBigLpPad + 16 * kk);
 #pragma unroll
       for (int sb = 0; sb < 4; ++sb) {
         acc[sb][0] = LowP<MODE>::mfma(v[sb], g0, acc[sb][0]);
         acc[sb][1] = LowP<MODE>::mfma(v[sb], g1, acc[sb][1]);
       }
     }
-    if (q + 1 < nkb) coop_store(buf ^ 1);
+    if (q + 1 < nkb) coop_store(buf ^ 1, q + 1);
     __syncthreads();
   }
   const int hstride = 128 + 4;
@@ -895,16 +1004,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
             Hs[(sb * 32 + acc_col(v, half)) * hstride + rw * 64 + jb * 32 + (lane & 31)] = acc[sb][jb][v];
     }
     __syncthreads();
-    gather_round(I, Hs, hstride, S0, min(S0 + 128, k), tacc);
+    gacc.round(I, Hs, hstride, S0, min(S0 + 128, k));
     __syncthreads();
   }
-  float* dst = I.part + ((size_t)lt * a.nsg + sg) * I.E123;
-#pragma unroll
-  for (int i = 0; i < kMaxOwned; ++i) {
-    const int x = tid + i * kThreads;
-    if (x >= I.E123) break;
-    dst[x] = tacc[i];
-  }
+  gacc.store(I, I.part + ((size_t)lt * a.nsg + sg) * I.E123);
 }
 
 // =====================================================================================
@@ -1183,14 +1286,20 @@ __global__ void k_prep_v(const float* V, int k, int kp, float* Vf, float* Va, fl
 
 //   Vf_lo[((cb * nhs + kk) * 64 + l) * 8 + j] = V[16*kk + 8*(l/32) + j][cb*32 + l%32]
 //   Va_lo[(((sb * nkb + cb) * 2 + p) * 64 + l) * 8 + j] = V[sb*32 + l%32][cb*32 + acc_col(8p + j, l/32)]
+//   Vp_lo[s * kp + c] = V[s][c] (zero-padded)
 template <int MODE>
-__global__ void k_prep_v_lp(const float* V, int k, int kp, void* Vf_lo, void* Va_lo) {
+__global__ void k_prep_v_lp(const float* V, int k, int kp, void* Vf_lo, void* Va_lo, void* Vp_lo) {
   typedef typename LowP<MODE>::h H;
   H* vf = reinterpret_cast<H*>(Vf_lo);
   H* va = reinterpret_cast<H*>(Va_lo);
+  H* vp = reinterpret_cast<H*>(Vp_lo);
   const int nkb = kp / 32, nhs = kp / 16;
   const int64_t n = (int64_t)kp * kp;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    {
+      const int s = (int)(e / kp), c = (int)(e % kp);
+      vp[e] = (H)((s < k && c < k) ? V[(int64_t)s * k + c] : 0.f);
+    }
     const int j = (int)(e & 7);
     const int l = (int)((e >> 3) & 63);
     const int64_t blk = e >> 9;
@@ -1293,26 +1402,42 @@ void launch_colnorm(const StageArgs& a, int nslices_total, int ninst, hipStream_
   hipLaunchKernelGGL(k_colnorm_finish, dim3(ninst), dim3(kThreads), 0, st, a);
 }
 
-void launch_adjoint_big(const StageArgs& a, int ntiles_total, int mode, hipStream_t st) {
-  const dim3 g(ntiles_total, a.nsg), b(kThreads);
+template <int GV>
+static void launch_adjoint_big_gv(const StageArgs& a, int ntiles_total, int mode, hipStream_t st) {
+  const dim3 g(((ntiles_total + 7) / 8) * 8 * a.nsg), b(kThreads);
   if (mode == kFP32) {
     const int lds = std::max(2 * (128 + 256) * kBigPad, 128 * (128 + 4));
-    hipLaunchKernelGGL(k_adjoint_big, g, b, lds * 4, st, a);
+    hipLaunchKernelGGL(k_adjoint_big<GV>, g, b, lds * 4, st, a);
   } else {
-    const int lds = std::max((2 * (128 + 256) * kBigLpPad + 1) / 2, 128 * (128 + 4));
-    if (mode == kBF16) hipLaunchKernelGGL(k_adjoint_big_lp<kBF16>, g, b, lds * 4, st, a);
-    if (mode == kFP16) hipLaunchKernelGGL(k_adjoint_big_lp<kFP16>, g, b, lds * 4, st, a);
+    const int lds = kBigLpStage + a.kp;
+    if (mode == kBF16) hipLaunchKernelGGL((k_adjoint_big_lp<kBF16, GV>), g, b, lds * 4, st, a);
+    if (mode == kFP16) hipLaunchKernelGGL((k_adjoint_big_lp<kFP16, GV>), g, b, lds * 4, st, a);
   }
 }
 
-void launch_adjoint(const StageArgs& a, int ntiles_total, int lds_floats, int mode, hipStream_t st) {
-  const dim3 g(ntiles_total, a.nsg), b(kThreads);
-  if (mode == kBF16)
-    hipLaunchKernelGGL(k_adjoint<kBF16>, g, b, lds_floats * 4, st, a);
-  else if (mode == kFP16)
-    hipLaunchKernelGGL(k_adjoint<kFP16>, g, b, lds_floats * 4, st, a);
+void launch_adjoint_big(const StageArgs& a, int ntiles_total, int mode, int gv, hipStream_t st) {
+  if (gv == 8)
+    launch_adjoint_big_gv<8>(a, ntiles_total, mode, st);
   else
-    hipLaunchKernelGGL(k_adjoint<kFP32>, g, b, lds_floats * 4, st, a);
+    launch_adjoint_big_gv<0>(a, ntiles_total, mode, st);
+}
+
+template <int GV>
+static void launch_adjoint_gv(const StageArgs& a, int ntiles_total, int lds_floats, int mode, hipStream_t st) {
+  const dim3 g(((ntiles_total + 7) / 8) * 8 * a.nsg), b(kThreads);
+  if (mode == kBF16)
+    hipLaunchKernelGGL((k_adjoint<kBF16, GV>), g, b, lds_floats * 4, st, a);
+  else if (mode == kFP16)
+    hipLaunchKernelGGL((k_adjoint<kFP16, GV>), g, b, lds_floats * 4, st, a);
+  else
+    hipLaunchKernelGGL((k_adjoint<kFP32, GV>), g, b, lds_floats * 4, st, a);
+}
+
+void launch_adjoint(const StageArgs& a, int ntiles_total, int lds_floats, int mode, int gv, hipStream_t st) {
+  if (gv == 8)
+    launch_adjoint_gv<8>(a, ntiles_total, lds_floats, mode, st);
+  else
+    launch_adjoint_gv<0>(a, ntiles_total, lds_floats, mode, st);
 }
 
 void launch_lstep(const StageArgs& a, int nlblocks_total, hipStream_t st) {
@@ -1330,11 +1455,11 @@ void launch_forward(const StageArgs& a, int ntiles_total, int lds_floats, int mo
 }
 
 void launch_prep_v(const float* V, int k, int kp, float* Vf, float* Va, float* Vp, void* Vf_lo, void* Va_lo,
-                   int prec, hipStream_t st) {
+                   void* Vp_lo, int prec, hipStream_t st) {
   const dim3 g(grid_for((int64_t)kp * kp, 4096)), b(kThreads);
   hipLaunchKernelGGL(k_prep_v, g, b, 0, st, V, k, kp, Vf, Va, Vp);
-  if (prec == kBF16) hipLaunchKernelGGL(k_prep_v_lp<kBF16>, g, b, 0, st, V, k, kp, Vf_lo, Va_lo);
-  if (prec == kFP16) hipLaunchKernelGGL(k_prep_v_lp<kFP16>, g, b, 0, st, V, k, kp, Vf_lo, Va_lo);
+  if (prec == kBF16) hipLaunchKernelGGL(k_prep_v_lp<kBF16>, g, b, 0, st, V, k, kp, Vf_lo, Va_lo, Vp_lo);
+  if (prec == kFP16) hipLaunchKernelGGL(k_prep_v_lp<kFP16>, g, b, 0, st, V, k, kp, Vf_lo, Va_lo, Vp_lo);
 }
 
 void launch_check_v(const float* V, int k, float* out, hipStream_t st) {

@@ -120,6 +120,12 @@ static int lds_forward_floats(const Plan& p, int kp) {
   return std::max(h32, hlp) + 2 * nrc * CG + nrc * ncc;
 }
 
+// the line-owning col2im gather: innermost kernel extent 4, innermost tile extent 8,
+// at most two box lines per thread
+static bool lines_gather_fits(const Plan& p) {
+  return p.k[2] == 4 && p.b[2] == 8 && p.E[0] * p.E[1] <= 2 * kThreads;
+}
+
 static int lds_adjoint_floats(const Plan& p, int kp) {
   // staged H^T of one round: (offsets per round) x (tile rows + 4)
   const int SGW = std::min(kp, kGroup);
@@ -180,7 +186,9 @@ static Plan make_plan(const int m[3], const int k[3], int kp) {
         const double upw = (double)(bm / kRowUnit) * (std::min(kp, kGroup) / kColUnit) / 4.0;
         const double eff = wgs >= slots ? 1.0 : 0.5 + 0.5 * wgs / slots;
         const double inner = 1.0 + 0.005 * std::log2(32.0 / std::min(b2, 32));
-        const double cost = rounds * (std::max(upw, 1.0) + 0.5) / eff * padded * (1.0 + halo) * inner;
+        // tiles that admit the line-owning col2im gather (innermost kernel extent 4)
+        const double gather = (k[2] == 4 && !lines_gather_fits(p)) ? 1.3 : 1.0;
+        const double cost = rounds * (std::max(upw, 1.0) + 0.5) / eff * padded * (1.0 + halo) * inner * gather;
         if (cost < best_cost - 1e-12) {
           best_cost = cost;
           best = p;
@@ -259,7 +267,7 @@ struct Group {
   int kd[3];
   int k, kp, nsg, ncg, prec;
   const float* Vsrc = nullptr;
-  DevBuf Vf, Va, Vp, Vlo_f, Vlo_a;
+  DevBuf Vf, Va, Vp, Vlo_f, Vlo_a, Vlo_p;
   bool big = false;  // kp >= 512: 128-row tiles and the tiled adjoint
   std::vector<Member*> members;
   int capacity;
@@ -267,6 +275,7 @@ struct Group {
   std::vector<int> free_slots;
   DevBuf inst, tiles, lblocks, slices;
   int ntiles_total = 0, nlblk_total = 0, nslice_total = 0, lds_fwd = 0, lds_adj = 0;
+  int gv = 0;  // col2im gather variant of the adjoint launches
   bool dirty = true;
   hipGraphExec_t gexec = nullptr;
   int graph_rounds = 0;
@@ -304,8 +313,9 @@ struct Group {
     if (prec != kFP32) {
       Vlo_f.ensure(budget, n * 2);
       Vlo_a.ensure(budget, n * 2);
+      Vlo_p.ensure(budget, n * 2);
     }
-    launch_prep_v(V, k, kp, Vf.as<float>(), Va.as<float>(), Vp.as<float>(), Vlo_f.p, Vlo_a.p, prec, st);
+    launch_prep_v(V, k, kp, Vf.as<float>(), Va.as<float>(), Vp.as<float>(), Vlo_f.p, Vlo_a.p, Vlo_p.p, prec, st);
     HIPCK(hipGetLastError());
   }
 
@@ -394,8 +404,10 @@ struct Group {
     std::vector<InstDev> ds;
     std::vector<int2> tl, lb, sl;
     lds_fwd = lds_adj = 0;
+    gv = members.empty() ? 0 : 8;
     for (size_t i = 0; i < members.size(); ++i) {
       const Member* mb = members[i];
+      if (!lines_gather_fits(mb->plan)) gv = 0;
       ds.push_back(mb->dev);
       for (int t = 0; t < mb->plan.ntiles; ++t) tl.push_back(make_int2((int)i, t));
       for (int t = 0; t < mb->plan.nlblk; ++t) lb.push_back(make_int2((int)i, t));
@@ -435,25 +447,33 @@ struct Group {
     a.Vp = Vp.as<float>();
     a.Vf_lo = Vlo_f.p;
     a.Va_lo = Vlo_a.p;
+    a.Vp_lo = Vlo_p.p;
     a.kp = kp;
     a.k = k;
     a.nsg = nsg;
     a.ncg = ncg;
+    a.ntiles = ntiles_total;
     a.tiles_per_slice = kTilesPerSlice;
     a.prec = prec;
     return a;
   }
 
+  // FP32 adjoint (initialisation, FP32 solves, refresh iterations) and, for the reduced
+  // precisions, the delta adjoint; each returns at once for instances it does not serve
+  void launch_adjoints(const StageArgs& a, hipStream_t st) const {
+    if (kp >= 512) {
+      launch_adjoint_big(a, ntiles_total, kFP32, gv, st);
+      if (prec != kFP32) launch_adjoint_big(a, ntiles_total, prec, gv, st);
+    } else {
+      launch_adjoint(a, ntiles_total, lds_adj, kFP32, gv, st);
+      if (prec != kFP32) launch_adjoint(a, ntiles_total, lds_adj, prec, gv, st);
+    }
+  }
+
   void launch_round(hipStream_t st) {
     const StageArgs a = args();
     launch_colnorm(a, nslice_total, (int)members.size(), st);
-    if (kp >= 512) {
-      launch_adjoint_big(a, ntiles_total, kFP32, st);
-      if (prec != kFP32) launch_adjoint_big(a, ntiles_total, prec, st);
-    } else {
-      launch_adjoint(a, ntiles_total, lds_adj, kFP32, st);
-      if (prec != kFP32) launch_adjoint(a, ntiles_total, lds_adj, prec, st);
-    }
+    launch_adjoints(a, st);
     launch_lstep(a, nlblk_total, st);
     launch_forward(a, ntiles_total, lds_fwd, kFP32, st);
     if (prec != kFP32) launch_forward(a, ntiles_total, lds_fwd, prec, st);
@@ -470,13 +490,7 @@ struct Group {
     launch_colnorm(a, nslice_total, (int)members.size(), st);
     HIPCK(hipEventRecord(prof->ev[1], st));
     HIPCK(hipEventRecord(prof->ev[2], st));
-    if (kp >= 512) {
-      launch_adjoint_big(a, ntiles_total, kFP32, st);
-      if (prec != kFP32) launch_adjoint_big(a, ntiles_total, prec, st);
-    } else {
-      launch_adjoint(a, ntiles_total, lds_adj, kFP32, st);
-      if (prec != kFP32) launch_adjoint(a, ntiles_total, lds_adj, prec, st);
-    }
+    launch_adjoints(a, st);
     HIPCK(hipEventRecord(prof->ev[3], st));
     HIPCK(hipEventRecord(prof->ev[4], st));
     launch_lstep(a, nlblk_total, st);
@@ -1093,7 +1107,9 @@ static icnnm_status do_submit(icnnm_ctx* c, const icnnm_shape* shape, const floa
   const int nsg = (kp + kGroup - 1) / kGroup;
   const Plan p = make_plan(r.m, r.kd, kp);
   r.bytes = member_bytes(p, kp, nsg, nsg, params->precision);
-  if (r.bytes + (size_t)kp * kp * 8 + sizeof(InstState) * kServeSlots > c->budget.limit)
+  // V operand copies: three FP32 layouts, three more in BF16/FP16 for the reduced precisions
+  const size_t vbytes = (size_t)kp * kp * (12 + (params->precision != 0 ? 6 : 0));
+  if (r.bytes + vbytes + sizeof(InstState) * kServeSlots > c->budget.limit)
     throw Error(ICNNM_E_BUDGET, "request alone exceeds the HBM budget");
   std::lock_guard<std::mutex> lk(c->q_mu);
   if (!c->server.joinable()) {

@@ -25,6 +25,13 @@ constexpr int kLanesPerElem = kThreads / kLStepElems;      // L-step lanes per o
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
+// global address space qualifier for device code (the host pass sees plain types)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GLOBAL_AS __attribute__((address_space(1)))
+#else
+#define GLOBAL_AS
+#endif
+
 // Reduced-precision MFMA: v_mfma_f32_32x32x16_{bf16,f16}. Lane l supplies the eight
 // consecutive K entries (l/32)*8 .. (l/32)*8+7 of row l%32 of A and of column l%32 of B;
 // the accumulator layout is that of the 32x32 FP32 MFMA.
@@ -35,6 +42,7 @@ struct LowP<kBF16> {
   typedef __bf16 h;
   typedef __bf16 v8 __attribute__((ext_vector_type(8)));
   typedef __bf16 v4 __attribute__((ext_vector_type(4)));
+  typedef GLOBAL_AS const v8 gv8;
   static __device__ __forceinline__ floatx16 mfma(v8 a, v8 b, floatx16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
   }
@@ -44,6 +52,7 @@ struct LowP<kFP16> {
   typedef _Float16 h;
   typedef _Float16 v8 __attribute__((ext_vector_type(8)));
   typedef _Float16 v4 __attribute__((ext_vector_type(4)));
+  typedef GLOBAL_AS const v8 gv8;
   static __device__ __forceinline__ floatx16 mfma(v8 a, v8 b, floatx16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
   }
@@ -65,14 +74,17 @@ __device__ __forceinline__ bool runs_iteration(const InstDev& I, const InstState
 typedef __attribute__((address_space(1))) const float4 gcfloat4;
 typedef __attribute__((address_space(1))) float4 gfloat4;
 typedef __attribute__((address_space(1))) const float gcfloat;
+typedef __attribute__((address_space(1))) const uint4 gcuint4;
 #else
 typedef const float4 gcfloat4;
 typedef float4 gfloat4;
 typedef const float gcfloat;
+typedef const uint4 gcuint4;
 #endif
 __device__ __forceinline__ gcfloat4* gc4(const void* p) { return (gcfloat4*)(p); }
 __device__ __forceinline__ gfloat4* g4(void* p) { return (gfloat4*)(p); }
 __device__ __forceinline__ gcfloat* gc1(const void* p) { return (gcfloat*)(p); }
+__device__ __forceinline__ gcuint4* gcu4(const void* p) { return (gcuint4*)(p); }
 
 __device__ __forceinline__ int wrapi(int v, int m) {
   v %= m;
@@ -309,37 +321,57 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
     typedef typename LowP<MODE>::v8 V8;
     typedef typename LowP<MODE>::v4 V4;
     const V4* e4 = reinterpret_cast<const V4*>(halo);
-    const uint4* vf0 = reinterpret_cast<const uint4*>(a.Vf_lo) + (size_t)(c0 / 32) * nhs * 64 + lane;
-    const uint4* vf1 = vf0 + (size_t)nhs * 64;
-    uint4 an0, an1;
-    V4 bn[2][2];
-    auto load_step = [&](int kk) {
-      an0 = vf0[(size_t)kk * 64];
-      an1 = vf1[(size_t)kk * 64];
+    // The V fragments come from L2 with a latency of many k-steps (four MFMAs each):
+    // they are loaded kPf steps ahead into a ring of registers; the LDS reads of D run
+    // one step ahead. Each step issues its MFMAs first and then refills the ring slot
+    // and the halo buffer it has just consumed, so the loads land in the registers
+    // the step read (no copies, exact wait counts). nhs is a multiple of kPf (kp is a
+    // multiple of 64).
+    constexpr int kPf = 4;
+    typedef typename LowP<MODE>::gv8 GV8;
+    GV8* vf0 = reinterpret_cast<GV8*>(gc4(a.Vf_lo)) + (size_t)(c0 / 32) * nhs * 64 + lane;
+    GV8* vf1 = vf0 + (size_t)nhs * 64;
+    V8 ra[kPf][2];
+    V4 bn[2][2][2];  // [step parity][row block][offset run]
+    auto load_d = [&](int kk, int slot) {
       const int2 ot = *reinterpret_cast<const int2*>(offs2 + kk * 4 + half * 2);
 #pragma unroll
       for (int ib = 0; ib < 2; ++ib) {
-        bn[ib][0] = e4[base[ib] - ot.x];
-        bn[ib][1] = e4[base[ib] - ot.y];
+        bn[slot][ib][0] = e4[base[ib] - ot.x];
+        bn[slot][ib][1] = e4[base[ib] - ot.y];
       }
     };
-    load_step(0);
-    for (int kk = 0; kk < nhs; ++kk) {
-      V8 av0, av1, bv0, bv1;
-      __builtin_memcpy(&av0, &an0, 16);
-      __builtin_memcpy(&av1, &an1, 16);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        bv0[j] = bn[0][0][j];
-        bv0[4 + j] = bn[0][1][j];
-        bv1[j] = bn[1][0][j];
-        bv1[4 + j] = bn[1][1][j];
+    for (int i = 0; i < kPf; ++i) {
+      ra[i][0] = vf0[(size_t)i * 64];
+      ra[i][1] = vf1[(size_t)i * 64];
+    }
+    load_d(0, 0);
+    for (int kb = 0; kb < nhs; kb += kPf) {
+#pragma unroll
+      for (int i = 0; i < kPf; ++i) {
+        const int kk = kb + i, cur = i & 1;
+        V8 bv0, bv1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          bv0[j] = bn[cur][0][0][j];
+          bv0[4 + j] = bn[cur][0][1][j];
+          bv1[j] = bn[cur][1][0][j];
+          bv1[4 + j] = bn[cur][1][1][j];
+        }
+        // the halo reads of the next step go to the other parity buffer
+        load_d(min(kk + 1, nhs - 1), cur ^ 1);
+        acc[0][0] = LowP<MODE>::mfma(ra[i][0], bv0, acc[0][0]);
+        acc[0][1] = LowP<MODE>::mfma(ra[i][0], bv1, acc[0][1]);
+        acc[1][0] = LowP<MODE>::mfma(ra[i][1], bv0, acc[1][0]);
+        acc[1][1] = LowP<MODE>::mfma(ra[i][1], bv1, acc[1][1]);
+        __builtin_amdgcn_sched_barrier(0);
+        // unconditional (clamped) refill keeps the body branch-free; the last steps
+        // reload the final fragments harmlessly
+        const int kn = min(kk + kPf, nhs - 1);
+        ra[i][0] = vf0[(size_t)kn * 64];
+        ra[i][1] = vf1[(size_t)kn * 64];
       }
-      if (kk + 1 < nhs) load_step(kk + 1);
-      acc[0][0] = LowP<MODE>::mfma(av0, bv0, acc[0][0]);
-      acc[0][1] = LowP<MODE>::mfma(av0, bv1, acc[0][1]);
-      acc[1][0] = LowP<MODE>::mfma(av1, bv0, acc[1][0]);
-      acc[1][1] = LowP<MODE>::mfma(av1, bv1, acc[1][1]);
     }
     }
 
@@ -706,8 +738,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
     // it to the running A_k^*(G V^T)
     typedef typename LowP<MODE>::v8 V8;
     const float rp = (float)(1.0 / I.st->ratio_prev);
-    const uint4* va0 = reinterpret_cast<const uint4*>(a.Va_lo) + (size_t)(s0 / 32) * nkb * 128 + lane;
-    const uint4* va1 = va0 + (size_t)nkb * 128;
+    gcuint4* va0 = gcu4(a.Va_lo) + (size_t)(s0 / 32) * nkb * 128 + lane;
+    gcuint4* va1 = va0 + (size_t)nkb * 128;
     const size_t row0 = ((size_t)lt * (bm / 32) + rc * 2) * nkb;
     float4 fu[2][2], fq[2][2], fs[2];
     uint4 fv0, fv1;

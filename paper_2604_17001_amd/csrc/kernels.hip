@@ -499,17 +499,19 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
 // land on them (t = j - s), in a fixed order. No atomics: the result is
 // deterministic and independent of how the work was scheduled.
 // =====================================================================================
-constexpr int kMaxOwned = 16;  // box positions per thread (E123 <= 4096)
+constexpr int kMaxOwned = 16;     // box positions per thread of the per-unit adjoint (E123 <= 4096)
+constexpr int kMaxOwnedBig = 24;  // ... of the large-kernel adjoints (E123 <= 6144)
 
 // col2im gather: thread-owned box position x (box coordinates) receives
 // H[j = x - (k - 1) + s][s] for the staged kernel offsets s in [S0, S1) whose row j
 // lies inside the tile; Hs[s - S0][row] holds the staged H^T. Fixed order.
+template <int CAP>
 __device__ __forceinline__ void gather_round(const InstDev& I, const float* Hs, int hstride, int S0, int S1,
                                              float* tacc) {
   const int k0 = I.k[0], k1 = I.k[1], k2 = I.k[2], k12 = k1 * k2;
   const int E123 = I.E123, E12 = I.E[1] * I.E[2];
 #pragma unroll
-  for (int i = 0; i < kMaxOwned; ++i) {
+  for (int i = 0; i < CAP; ++i) {
     const int x = threadIdx.x + i * kThreads;
     if (x >= E123) break;
     const int x0 = x / E12, rem = x - x0 * E12;
@@ -588,26 +590,27 @@ __device__ __forceinline__ void gather_lines(const InstDev& I, const float* Hs, 
   }
 }
 
-// Per-thread col2im accumulators of one adjoint workgroup. GV = 0: box positions
-// (any geometry, E123 <= 4096); GV = 8: box lines for an innermost kernel extent of 4
-// and tile rows of 8 along the innermost dimension (at most 512 lines). The host picks
-// GV per launch from the plans of the instances it covers.
-template <int GV>
+// Per-thread col2im accumulators of one adjoint workgroup. GV = 0: box positions, any
+// geometry, CAP positions per thread (E123 <= 256 CAP); GV = 8: box lines for an
+// innermost kernel extent of 4 and tile rows of 8 along the innermost dimension (at
+// most 512 lines). The host picks GV per launch from the plans of the instances it
+// covers.
+template <int GV, int CAP = kMaxOwned>
 struct GatherAcc;
 
-template <>
-struct GatherAcc<0> {
-  float t[kMaxOwned];
+template <int CAP>
+struct GatherAcc<0, CAP> {
+  float t[CAP];
   __device__ __forceinline__ void zero() {
 #pragma unroll
-    for (int i = 0; i < kMaxOwned; ++i) t[i] = 0.f;
+    for (int i = 0; i < CAP; ++i) t[i] = 0.f;
   }
   __device__ __forceinline__ void round(const InstDev& I, const float* Hs, int hstride, int S0, int S1) {
-    gather_round(I, Hs, hstride, S0, S1, t);
+    gather_round<CAP>(I, Hs, hstride, S0, S1, t);
   }
   __device__ __forceinline__ void store(const InstDev& I, float* dst) const {
 #pragma unroll
-    for (int i = 0; i < kMaxOwned; ++i) {
+    for (int i = 0; i < CAP; ++i) {
       const int x = threadIdx.x + i * kThreads;
       if (x >= I.E123) break;
       dst[x] = t[i];
@@ -615,8 +618,8 @@ struct GatherAcc<0> {
   }
 };
 
-template <>
-struct GatherAcc<8> {
+template <int CAP>
+struct GatherAcc<8, CAP> {
   static constexpr int kLines = 2, kE2 = 8 + 3;
   float t[kLines][kE2];
   __device__ __forceinline__ void zero() {
@@ -826,7 +829,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big(StageArgs a) {
   const int rw = wave & 1, sh = wave >> 1;             // row chunk, offset half
   float* Gs = smem;                                    // [2][128][kBigPad]
   float* Vs = smem + 2 * 128 * kBigPad;                // [2][256][kBigPad]
-  GatherAcc<GV> gacc;
+  GatherAcc<GV, kMaxOwnedBig> gacc;
   gacc.zero();
 
   floatx16 acc[4][2];
@@ -950,7 +953,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
   H* Vs = Gs + 2 * 128 * kBigLpPad;                    // [2][256][kBigLpPad]
   float* Ss = smem + kBigLpStage;                      // shrink factors [kp]
   for (int c = threadIdx.x; c < kp; c += kThreads) Ss[c] = I.s[c];
-  GatherAcc<GV> gacc;
+  GatherAcc<GV, kMaxOwnedBig> gacc;
   gacc.zero();
   floatx16 acc[4][2];
 #pragma unroll

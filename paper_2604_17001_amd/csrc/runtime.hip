@@ -168,7 +168,9 @@ static Plan make_plan(const int m[3], const int k[3], int kp) {
         p.ntiles = (int)ntiles;
         if (lds_forward_floats(p, kp) * 4 > 150 * 1024) continue;
         {
-          if (bm / kRowUnit > 4 || p.E123 > 4096) continue;
+          // box positions per thread of the col2im gather: 16 (per-unit adjoint),
+          // 24 (large-kernel adjoint)
+          if (bm / kRowUnit > 4 || p.E123 > (kp >= 512 ? 6144 : 4096)) continue;
           if (lds_adjoint_floats(p, kp) * 4 > 80 * 1024) continue;
         }
         if (p.E[0] > 65535 || p.E[1] > 65535 || p.E[2] > 65535 || ntiles > 65535 * 16) continue;

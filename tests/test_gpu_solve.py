@@ -71,6 +71,29 @@ def test_solve_parity_small(lib, dims, kdims, pm, seed):
     assert abs(info["theta_final"] - oi["theta_final"]) <= 1e-5 * oi["theta_final"]
 
 
+# The image and video kernel sizes of the paper's experiments (Section V: square
+# kernels up to 43x43 on images, 13x13x13 on videos) on synthetic tensors small
+# enough for the oracle: k = 1849 (padded to 2048) and k = 2197 (padded to 2304,
+# 9 offset groups, 5120-position halo boxes). Few iterations keep the oracle short.
+BIG_K = [
+    ((64, 64), (43, 43), 0.5, 21, 8),
+    ((20, 20, 16), (13, 13, 13), 0.4, 22, 6),
+]
+
+
+@pytest.mark.parametrize("dims,kdims,pm,seed,iters", BIG_K)
+def test_solve_parity_paper_kernel_sizes(lib, dims, kdims, pm, seed, iters):
+    prob, V32 = _case(dims, kdims, pm, seed, b=2)
+    L, info = _gpu_solve(lib, prob, V32, iters)
+    Lo, oi = O.solve(prob.M, prob.mask, V32.astype(np.float64), kdims, iters)
+    err = _relerr(L, Lo)
+    print(f"[gpu] rel.err {err:.3e}", flush=True)
+    assert info["iters"] == iters
+    assert err <= TOL32, err
+    obs = prob.mask != 0
+    assert np.array_equal(L[obs], prob.M[obs])
+
+
 def test_zero_iterations_is_zero_fill(lib):
     prob, V32 = _case((12, 10, 8), (3, 3, 2), 0.4, 7)
     L, info = _gpu_solve(lib, prob, V32, 0)

@@ -270,7 +270,7 @@ struct Group {
   int k, kp, nsg, ncg, prec;
   const float* Vsrc = nullptr;
   DevBuf Vf, Va, Vp, Vlo_f, Vlo_a, Vlo_p;
-  bool big = false;  // kp >= 512: 128-row tiles and the tiled adjoint
+  bool big = false;  // adjoint tiled for operand reuse: kp a multiple of 256, 128-row tiles
   std::vector<Member*> members;
   int capacity;
   DevBuf states;  // InstState[capacity]
@@ -407,9 +407,11 @@ struct Group {
     std::vector<int2> tl, lb, sl;
     lds_fwd = lds_adj = 0;
     gv = members.empty() ? 0 : 8;
+    big = kp % kGroup == 0;
     for (size_t i = 0; i < members.size(); ++i) {
       const Member* mb = members[i];
       if (!lines_gather_fits(mb->plan)) gv = 0;
+      if (mb->plan.bm != 128) big = false;
       ds.push_back(mb->dev);
       for (int t = 0; t < mb->plan.ntiles; ++t) tl.push_back(make_int2((int)i, t));
       for (int t = 0; t < mb->plan.nlblk; ++t) lb.push_back(make_int2((int)i, t));
@@ -463,7 +465,7 @@ struct Group {
   // FP32 adjoint (initialisation, FP32 solves, refresh iterations) and, for the reduced
   // precisions, the delta adjoint; each returns at once for instances it does not serve
   void launch_adjoints(const StageArgs& a, hipStream_t st) const {
-    if (kp >= 512) {
+    if (big) {
       launch_adjoint_big(a, ntiles_total, kFP32, gv, st);
       if (prec != kFP32) launch_adjoint_big(a, ntiles_total, prec, gv, st);
     } else {

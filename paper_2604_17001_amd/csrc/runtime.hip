@@ -190,7 +190,9 @@ static Plan make_plan(const int m[3], const int k[3], int kp) {
         const double inner = 1.0 + 0.005 * std::log2(32.0 / std::min(b2, 32));
         // tiles that admit the line-owning col2im gather (innermost kernel extent 4)
         const double gather = (k[2] == 4 && !lines_gather_fits(p)) ? 1.3 : 1.0;
-        const double cost = rounds * (std::max(upw, 1.0) + 0.5) / eff * padded * (1.0 + halo) * inner * gather;
+        // 128-row tiles admit the operand-reusing tiled adjoint when kp is a multiple of 256
+        const double tiled = (kp % kGroup == 0 && bm != 128) ? 1.3 : 1.0;
+        const double cost = rounds * (std::max(upw, 1.0) + 0.5) / eff * padded * (1.0 + halo) * inner * gather * tiled;
         if (cost < best_cost - 1e-12) {
           best_cost = cost;
           best = p;

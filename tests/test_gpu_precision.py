@@ -81,7 +81,8 @@ def test_precision_needs_innermost_kernel_multiple_of_4(lib):
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
-@pytest.mark.parametrize("name,factory", [("c1", inputs.c1_plain), ("c2", inputs.c2_plain)])
+@pytest.mark.parametrize("name,factory", [("c1", inputs.c1_plain), ("c2", inputs.c2_plain),
+                                          ("c3", inputs.c3_precision)])
 def test_config_reduced_precision_vs_stored_oracle(lib, prec, name, factory):
     if not os.path.exists(os.path.join(GOLD, f"{name}_L.npy")):
         pytest.skip("stored oracle result missing")

@@ -172,6 +172,78 @@ __device__ __forceinline__ void tile_origin(int lt, const InstDev& I, int* o) {
   o[2] = n2 * I.b[2];
 }
 
+// Box position -> source coordinates of a tile's circular halo. Quotients use a float
+// reciprocal with a +-1 correction (exact for the box sizes here, < 2^22); before
+// wrapping, coordinates lie in (-m, 3m) (k <= m, tile extent < 2m), so two
+// conditional subtractions and one addition wrap them.
+__device__ __forceinline__ int divq(int x, int d, float rd) {
+  int q = (int)((float)x * rd);
+  q += ((q + 1) * d <= x) ? 1 : 0;
+  q -= (q * d > x) ? 1 : 0;
+  return q;
+}
+__device__ __forceinline__ int wrap3(int v, int m) {
+  v += v < 0 ? m : 0;
+  v -= v >= m ? m : 0;
+  v -= v >= m ? m : 0;
+  return v;
+}
+struct HaloMap {
+  int E12, E2, s0, s1, s2, m0, m1, m2;  // s_d = tile origin - (k_d - 1)
+  float r12, r2;
+  __device__ __forceinline__ HaloMap(const InstDev& I, const int* o) {
+    E2 = I.E[2];
+    E12 = I.E[1] * E2;
+    r12 = 1.f / (float)E12;
+    r2 = 1.f / (float)E2;
+    s0 = o[0] - (I.k[0] - 1);
+    s1 = o[1] - (I.k[1] - 1);
+    s2 = o[2] - (I.k[2] - 1);
+    m0 = I.m[0];
+    m1 = I.m[1];
+    m2 = I.m[2];
+  }
+  // flat index of the (wrapped) row (g0, g1, 0) and the unwrapped innermost coordinate
+  __device__ __forceinline__ int64_t row(int x, int& c2) const {
+    const int x0 = divq(x, E12, r12), rem = x - x0 * E12;
+    const int x1 = divq(rem, E2, r2), x2 = rem - x1 * E2;
+    c2 = s2 + x2;
+    return ((int64_t)wrap3(s0 + x0, m0) * m1 + wrap3(s1 + x1, m1)) * m2;
+  }
+};
+
+// Sums of 16 per-lane values over the 32 lanes of each half-wavefront, by halving
+// exchanges (16 shuffles instead of 80). On return v[0] holds, in lanes l and l ^ 1,
+// the total of value index vi = 8 b4 + 4 b3 + 2 b2 + b1 (b_j = bit j of l).
+__device__ __forceinline__ float half_sum16(float (&v)[16], int lane, int& vi) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const bool hi = lane & 16;
+    const float send = hi ? v[i] : v[i + 8], keep = hi ? v[i + 8] : v[i];
+    v[i] = keep + __shfl_xor(send, 16, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const bool hi = lane & 8;
+    const float send = hi ? v[i] : v[i + 4], keep = hi ? v[i + 4] : v[i];
+    v[i] = keep + __shfl_xor(send, 8, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const bool hi = lane & 4;
+    const float send = hi ? v[i] : v[i + 2], keep = hi ? v[i + 2] : v[i];
+    v[i] = keep + __shfl_xor(send, 4, 64);
+  }
+  {
+    const bool hi = lane & 2;
+    const float send = hi ? v[0] : v[1], keep = hi ? v[1] : v[0];
+    v[0] = keep + __shfl_xor(send, 2, 64);
+  }
+  v[0] += __shfl_xor(v[0], 1, 64);
+  vi = ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 + ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
+  return v[0];
+}
+
 // =====================================================================================
 // forward: W = A_k(L) V, fused with the dual update and the next Q.
 //   init (phase kInit): U = 0, Q = W                      (Y^0 = 0)
@@ -217,16 +289,28 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   float* colw = colq + nrc * CG;                          // [nrc][CG]
   float* rred = colw + nrc * CG;                          // [nrc * ncc]
 
+  const HaloMap hm(I, o);
   if constexpr (MODE == kFP32) {
-    // halo of L over the tile box extended backwards by k - 1, with circular wrap
-    const float* L = I.L;
-    for (int x = tid; x < E123; x += kThreads) {
-      int x0 = x / E12, rem = x - x0 * E12;
-      int x1 = rem / I.E[2], x2 = rem - x1 * I.E[2];
-      int g0 = wrapi(o[0] - (I.k[0] - 1) + x0, I.m[0]);
-      int g1 = wrapi(o[1] - (I.k[1] - 1) + x1, I.m[1]);
-      int g2 = wrapi(o[2] - (I.k[2] - 1) + x2, I.m[2]);
-      halo[x] = L[((int64_t)g0 * I.m[1] + g1) * I.m[2] + g2];
+    // halo of L over the tile box extended backwards by k - 1, with circular wrap;
+    // eight positions per thread are loaded before any is stored
+    gcfloat* L = gc1(I.L);
+    for (int xb = tid; xb < E123; xb += 8 * kThreads) {
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int x = xb + j * kThreads;
+        v[j] = 0.f;
+        if (x < E123) {
+          int c2;
+          const int64_t r = hm.row(x, c2);
+          v[j] = L[r + wrap3(c2, hm.m2)];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int x = xb + j * kThreads;
+        if (x < E123) halo[x] = v[j];
+      }
     }
     for (int e = tid; e < kp; e += kThreads) {
       const int h = e >> 4, hf = (e >> 3) & 1, jj = e & 7;
@@ -235,17 +319,31 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   } else {
     typedef typename LowP<MODE>::h H;
     H* e4 = reinterpret_cast<H*>(halo);
-    const float* D = I.D;
-    for (int x = tid; x < E123; x += kThreads) {
-      int x0 = x / E12, rem = x - x0 * E12;
-      int x1 = rem / I.E[2], x2 = rem - x1 * I.E[2];
-      const int g0 = wrapi(o[0] - (I.k[0] - 1) + x0, I.m[0]);
-      const int g1 = wrapi(o[1] - (I.k[1] - 1) + x1, I.m[1]);
-      const float* row = D + ((int64_t)g0 * I.m[1] + g1) * I.m[2];
+    gcfloat* D = gc1(I.D);
+    // four positions per thread (16 values) are loaded before any is stored
+    for (int xb = tid; xb < E123; xb += 4 * kThreads) {
+      float v[4][4];
 #pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        const float v = (x2 >= d) ? row[wrapi(o[2] - (I.k[2] - 1) + x2 - d, I.m[2])] : 0.f;
-        e4[4 * x + d] = (H)v;
+      for (int j = 0; j < 4; ++j) {
+        const int x = xb + j * kThreads;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) v[j][d] = 0.f;
+        if (x < E123) {
+          int c2;
+          const int64_t r = hm.row(x, c2);
+          const int x2 = c2 - hm.s2;
+#pragma unroll
+          for (int d = 0; d < 4; ++d)
+            if (x2 >= d) v[j][d] = D[r + wrap3(c2 - d, hm.m2)];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int x = xb + j * kThreads;
+        if (x < E123) {
+#pragma unroll
+          for (int d = 0; d < 4; ++d) e4[4 * x + d] = (H)v[j][d];
+        }
       }
     }
     for (int e = tid; e < kp / 4; e += kThreads) offs2[e] = kernel_off(4 * e, I, k);
@@ -459,15 +557,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
           Qp[g] = make_float4(qn[0], qn[1], qn[2], qn[3]);
         }
       }
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const float q = half_sum(qs[v]);
-        const float w = half_sum(ws[v]);
-        if ((lane & 31) == 0) {
-          const int col = cc * kColUnit + cb * 32 + acc_col(v, half);
-          colq[rc * CG + col] = q;
-          colw[rc * CG + col] = w;
-        }
+      int vi;
+      const float q = half_sum16(qs, lane, vi);
+      const float w = half_sum16(ws, lane, vi);
+      if ((lane & 1) == 0) {
+        const int col = cc * kColUnit + cb * 32 + acc_col(vi, half);
+        colq[rc * CG + col] = q;
+        colw[rc * CG + col] = w;
       }
     }
     rsum = wave_sum(rsum);

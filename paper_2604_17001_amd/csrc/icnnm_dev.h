@@ -95,7 +95,9 @@ void launch_colnorm(const StageArgs& a, int nslices_total, int ninst, hipStream_
 // innermost tile extent 8, E0 E1 <= 512 for every instance of the launch)
 void launch_adjoint(const StageArgs& a, int ntiles_total, int lds_floats, int mode, int gv, hipStream_t st);
 void launch_lstep(const StageArgs& a, int nlblocks_total, hipStream_t st);
-void launch_forward(const StageArgs& a, int ntiles_total, int lds_floats, int mode, hipStream_t st);
+// rb: 32-row blocks per reduced-precision unit (2, or 4 when every instance of the
+// launch has tiles of a multiple of 128 rows); FP32 always uses 2
+void launch_forward(const StageArgs& a, int ntiles_total, int lds_floats, int mode, int rb, hipStream_t st);
 void launch_prep_v(const float* V, int k, int kp, float* Vf, float* Va, float* Vp, void* Vf_lo,
                    void* Va_lo, void* Vp_lo, int prec, hipStream_t st);
 // adjoint tiled for large kernels (kp >= 512, 128-row tiles)

@@ -252,8 +252,9 @@ __device__ __forceinline__ float half_sum16(float (&v)[16], int lane, int& vi) {
 // and per-tile partial sums of Q^2, W^2 (per column) and (Z - W)^2.
 // grid = (tiles, kp / 256 column groups); each wave takes (64 rows x 64 columns) units.
 // =====================================================================================
-template <int MODE>
+template <int MODE, int RB>
 __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
+  static_assert(RB == 2 || (RB == 4 && MODE != kFP32), "FP32 units have two row blocks");
   extern __shared__ float smem[];
   const int2 tt = a.tiles[blockIdx.x];
   const InstDev& I = a.inst[tt.x];
@@ -353,19 +354,24 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   const float ratio = (float)I.st->ratio;
   const int nkb = kp / 32;
   const int nhs = 2 * nkb;  // half-steps of 16 kernel offsets
-  for (int u = wave; u < nrc * ncc; u += 4) {
-    const int rc = u / ncc, cc = u % ncc;
+  // a unit is RB 32-row blocks x 64 columns: RB = 2 (FP32 and reduced precision) or
+  // 4 (reduced precision with 128-row multiples: each V fragment feeds four row
+  // blocks, halving the L2 traffic of V)
+  constexpr int kRpu = RB / 2;  // 64-row chunks per unit
+  const int nun = (nrc / kRpu) * ncc;
+  for (int u = wave; u < nun; u += 4) {
+    const int ru = u / ncc, cc = u % ncc;
     const int c0 = cg * CG + cc * kColUnit;
-    bool valid[2];
-    int base[2];
+    bool valid[RB];
+    int base[RB];
 #pragma unroll
-    for (int ib = 0; ib < 2; ++ib) base[ib] = row_base(rc * 64 + ib * 32 + (lane & 31), I, o, valid[ib]);
+    for (int ib = 0; ib < RB; ++ib) base[ib] = row_base(ru * RB * 32 + ib * 32 + (lane & 31), I, o, valid[ib]);
 
-    floatx16 acc[2][2];
+    floatx16 acc[2][RB];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = (floatx16)(0.0f);
+      for (int j = 0; j < RB; ++j) acc[i][j] = (floatx16)(0.0f);
 
     if constexpr (MODE == kFP32) {
     // V fragments: per (column block, offset block) 16 floats per lane in k-step
@@ -425,16 +431,16 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
     // and the halo buffer it has just consumed, so the loads land in the registers
     // the step read (no copies, exact wait counts). nhs is a multiple of kPf (kp is a
     // multiple of 64).
-    constexpr int kPf = 4;
+    constexpr int kPf = RB == 4 ? 2 : 4;  // eight MFMAs per step with four row blocks
     typedef typename LowP<MODE>::gv8 GV8;
     GV8* vf0 = reinterpret_cast<GV8*>(gc4(a.Vf_lo)) + (size_t)(c0 / 32) * nhs * 64 + lane;
     GV8* vf1 = vf0 + (size_t)nhs * 64;
     V8 ra[kPf][2];
-    V4 bn[2][2][2];  // [step parity][row block][offset run]
+    V4 bn[2][RB][2];  // [step parity][row block][offset run]
     auto load_d = [&](int kk, int slot) {
       const int2 ot = *reinterpret_cast<const int2*>(offs2 + kk * 4 + half * 2);
 #pragma unroll
-      for (int ib = 0; ib < 2; ++ib) {
+      for (int ib = 0; ib < RB; ++ib) {
         bn[slot][ib][0] = e4[base[ib] - ot.x];
         bn[slot][ib][1] = e4[base[ib] - ot.y];
       }
@@ -449,20 +455,20 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
 #pragma unroll
       for (int i = 0; i < kPf; ++i) {
         const int kk = kb + i, cur = i & 1;
-        V8 bv0, bv1;
+        V8 bv[RB];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          bv0[j] = bn[cur][0][0][j];
-          bv0[4 + j] = bn[cur][0][1][j];
-          bv1[j] = bn[cur][1][0][j];
-          bv1[4 + j] = bn[cur][1][1][j];
-        }
+        for (int ib = 0; ib < RB; ++ib)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            bv[ib][j] = bn[cur][ib][0][j];
+            bv[ib][4 + j] = bn[cur][ib][1][j];
+          }
         // the halo reads of the next step go to the other parity buffer
         load_d(min(kk + 1, nhs - 1), cur ^ 1);
-        acc[0][0] = LowP<MODE>::mfma(ra[i][0], bv0, acc[0][0]);
-        acc[0][1] = LowP<MODE>::mfma(ra[i][0], bv1, acc[0][1]);
-        acc[1][0] = LowP<MODE>::mfma(ra[i][1], bv0, acc[1][0]);
-        acc[1][1] = LowP<MODE>::mfma(ra[i][1], bv1, acc[1][1]);
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+          for (int ib = 0; ib < RB; ++ib) acc[cb][ib] = LowP<MODE>::mfma(ra[i][cb], bv[ib], acc[cb][ib]);
         __builtin_amdgcn_sched_barrier(0);
         // unconditional (clamped) refill keeps the body branch-free; the last steps
         // reload the final fragments harmlessly
@@ -473,14 +479,18 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
     }
     }
 
-    // fused epilogue over the four 32x32 pieces (cb, ib) of the unit; the U/Q loads
+    // fused epilogue over the 2 RB 32x32 pieces (cb, ib) of the unit; the U/Q loads
     // of a piece are issued two pieces ahead so that their latency overlaps the
     // arithmetic and stores of the pieces before it
-    float rsum = 0.f;
-    float4 bu[2][4], bq[2][4];
+    constexpr int kPieces = 2 * RB;
+    constexpr int kAhead = RB == 4 ? 1 : 2;  // pieces of U/Q loads in flight
+    float rsum[kRpu];
+#pragma unroll
+    for (int r = 0; r < kRpu; ++r) rsum[r] = 0.f;
+    float4 bu[kAhead][4], bq[kAhead][4];
     auto load_piece = [&](int pc, int slot) {
-      const int cb = pc >> 1, ib = pc & 1;
-      const size_t sidx = ((((size_t)lt * (I.bm / 32) + rc * 2 + ib) * nkb + c0 / 32 + cb) * 64 + lane) * 4;
+      const int cb = pc / RB, ib = pc % RB;
+      const size_t sidx = ((((size_t)lt * (I.bm / 32) + ru * RB + ib) * nkb + c0 / 32 + cb) * 64 + lane) * 4;
       gcfloat4* Up = gc4(I.U) + sidx;
       gcfloat4* Qp = gc4(I.Q) + sidx;
 #pragma unroll
@@ -490,8 +500,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
       }
     };
     if (!init) {
-      load_piece(0, 0);
-      load_piece(1, 1);
+#pragma unroll
+      for (int i = 0; i < kAhead; ++i) load_piece(i, i);
     }
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
@@ -506,8 +516,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) qs[v] = ws[v] = 0.f;
 #pragma unroll
-      for (int ib = 0; ib < 2; ++ib) {
-        const int pc = cb * 2 + ib, slot = pc & 1;
+      for (int ib = 0; ib < RB; ++ib) {
+        const int pc = cb * RB + ib, slot = pc % kAhead;
         float4 u4s[4], q4s[4];
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
@@ -518,8 +528,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
             q4s[g] = bq[slot][g];
           }
         }
-        if (!init && pc + 2 < 4) load_piece(pc + 2, slot);
-        const size_t sidx = ((((size_t)lt * (I.bm / 32) + rc * 2 + ib) * nkb + cblk) * 64 + lane) * 4;
+        if (!init && pc + kAhead < kPieces) load_piece(pc + kAhead, slot);
+        const size_t sidx = ((((size_t)lt * (I.bm / 32) + ru * RB + ib) * nkb + cblk) * 64 + lane) * 4;
         gfloat4* Up = g4(I.U) + sidx;
         gfloat4* Qp = g4(I.Q) + sidx;
 #pragma unroll
@@ -546,7 +556,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
               unew = (gg - w) * ratio;
               qnew = w - unew;
               const float d = z - w;
-              rsum += d * d;
+              rsum[ib / 2] += d * d;
             }
             un[e] = unew;
             qn[e] = qnew;
@@ -556,18 +566,26 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
           Up[g] = make_float4(un[0], un[1], un[2], un[3]);
           Qp[g] = make_float4(qn[0], qn[1], qn[2], qn[3]);
         }
-      }
-      int vi;
-      const float q = half_sum16(qs, lane, vi);
-      const float w = half_sum16(ws, lane, vi);
-      if ((lane & 1) == 0) {
-        const int col = cc * kColUnit + cb * 32 + acc_col(vi, half);
-        colq[rc * CG + col] = q;
-        colw[rc * CG + col] = w;
+        if (ib & 1) {  // column partials of one 64-row chunk
+          int vi;
+          const float q = half_sum16(qs, lane, vi);
+          const float w = half_sum16(ws, lane, vi);
+          if ((lane & 1) == 0) {
+            const int col = cc * kColUnit + cb * 32 + acc_col(vi, half);
+            const int rc = ru * kRpu + ib / 2;
+            colq[rc * CG + col] = q;
+            colw[rc * CG + col] = w;
+          }
+#pragma unroll
+          for (int v = 0; v < 16; ++v) qs[v] = ws[v] = 0.f;
+        }
       }
     }
-    rsum = wave_sum(rsum);
-    if (lane == 0) rred[u] = rsum;
+#pragma unroll
+    for (int r = 0; r < kRpu; ++r) {
+      const float rs = wave_sum(rsum[r]);
+      if (lane == 0) rred[(ru * kRpu + r) * ncc + cc] = rs;
+    }
   }
   __syncthreads();
   for (int c = tid; c < CG; c += kThreads) {
@@ -1575,14 +1593,22 @@ void launch_lstep(const StageArgs& a, int nlblocks_total, hipStream_t st) {
   hipLaunchKernelGGL(k_lstep, dim3(nlblocks_total), dim3(kThreads), 0, st, a);
 }
 
-void launch_forward(const StageArgs& a, int ntiles_total, int lds_floats, int mode, hipStream_t st) {
+void launch_forward(const StageArgs& a, int ntiles_total, int lds_floats, int mode, int rb, hipStream_t st) {
   const dim3 g(ntiles_total, a.ncg), b(kThreads);
-  if (mode == kBF16)
-    hipLaunchKernelGGL(k_forward<kBF16>, g, b, lds_floats * 4, st, a);
-  else if (mode == kFP16)
-    hipLaunchKernelGGL(k_forward<kFP16>, g, b, lds_floats * 4, st, a);
-  else
-    hipLaunchKernelGGL(k_forward<kFP32>, g, b, lds_floats * 4, st, a);
+  const size_t lds = (size_t)lds_floats * 4;
+  if (mode == kBF16) {
+    if (rb == 4)
+      hipLaunchKernelGGL((k_forward<kBF16, 4>), g, b, lds, st, a);
+    else
+      hipLaunchKernelGGL((k_forward<kBF16, 2>), g, b, lds, st, a);
+  } else if (mode == kFP16) {
+    if (rb == 4)
+      hipLaunchKernelGGL((k_forward<kFP16, 4>), g, b, lds, st, a);
+    else
+      hipLaunchKernelGGL((k_forward<kFP16, 2>), g, b, lds, st, a);
+  } else {
+    hipLaunchKernelGGL((k_forward<kFP32, 2>), g, b, lds, st, a);
+  }
 }
 
 void launch_prep_v(const float* V, int k, int kp, float* Vf, float* Va, float* Vp, void* Vf_lo, void* Va_lo,

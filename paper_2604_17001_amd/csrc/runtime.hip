@@ -280,6 +280,7 @@ struct Group {
   DevBuf inst, tiles, lblocks, slices;
   int ntiles_total = 0, nlblk_total = 0, nslice_total = 0, lds_fwd = 0, lds_adj = 0;
   int gv = 0;  // col2im gather variant of the adjoint launches
+  int lp_rb = 2;  // row blocks per reduced-precision forward unit
   bool dirty = true;
   hipGraphExec_t gexec = nullptr;
   int graph_rounds = 0;
@@ -410,10 +411,12 @@ struct Group {
     lds_fwd = lds_adj = 0;
     gv = members.empty() ? 0 : 8;
     big = kp % kGroup == 0;
+    lp_rb = members.empty() ? 2 : 4;
     for (size_t i = 0; i < members.size(); ++i) {
       const Member* mb = members[i];
       if (!lines_gather_fits(mb->plan)) gv = 0;
       if (mb->plan.bm != 128) big = false;
+      if (mb->plan.bm % 128 != 0) lp_rb = 2;
       ds.push_back(mb->dev);
       for (int t = 0; t < mb->plan.ntiles; ++t) tl.push_back(make_int2((int)i, t));
       for (int t = 0; t < mb->plan.nlblk; ++t) lb.push_back(make_int2((int)i, t));
@@ -481,8 +484,8 @@ struct Group {
     launch_colnorm(a, nslice_total, (int)members.size(), st);
     launch_adjoints(a, st);
     launch_lstep(a, nlblk_total, st);
-    launch_forward(a, ntiles_total, lds_fwd, kFP32, st);
-    if (prec != kFP32) launch_forward(a, ntiles_total, lds_fwd, prec, st);
+    launch_forward(a, ntiles_total, lds_fwd, kFP32, 2, st);
+    if (prec != kFP32) launch_forward(a, ntiles_total, lds_fwd, prec, lp_rb, st);
   }
 
   // one round with an event pair around each stage; returns after the events are read
@@ -502,8 +505,8 @@ struct Group {
     launch_lstep(a, nlblk_total, st);
     HIPCK(hipEventRecord(prof->ev[5], st));
     HIPCK(hipEventRecord(prof->ev[6], st));
-    launch_forward(a, ntiles_total, lds_fwd, kFP32, st);
-    if (prec != kFP32) launch_forward(a, ntiles_total, lds_fwd, prec, st);
+    launch_forward(a, ntiles_total, lds_fwd, kFP32, 2, st);
+    if (prec != kFP32) launch_forward(a, ntiles_total, lds_fwd, prec, lp_rb, st);
     HIPCK(hipEventRecord(prof->ev[7], st));
     HIPCK(hipEventSynchronize(prof->ev[7]));
     for (int i = 0; i < 4; ++i) {

@@ -253,13 +253,27 @@ def main():
         stages = {s: {"avg_us": 1e3 * ms / (nprof * working[s]), "launches": n} for s, (ms, n) in st.items()}
         dom = max(("forward", "adjoint"), key=lambda s: stages[s]["avg_us"])
         flops = 2.0 * m * k * k          # one m x k x k contraction per launch
-        achieved = flops / (stages[dom]["avg_us"] * 1e-6) / 1e12
-        peak = PEAKS["fp32_mfma"] if args.precision == "fp32" else PEAKS[f"{args.precision}_mfma"]
+        sec = stages[dom]["avg_us"] * 1e-6
+        # algorithmic state bytes per launch: the forward reads and writes U and Q, the
+        # adjoint reads them (FP32, m x kp entries each)
+        kp = ((k + 63) // 64) * 64 if k <= 256 else ((k + 255) // 256) * 256
+        abytes = (16.0 if dom == "forward" else 8.0) * m * kp
         tr = TRAFFIC.get((args.workload, args.precision, dom))
         traffic = tr["bytes"] if tr and tr["src"] == _kernel_src_hash() and args.iters == 0 else None
-        roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
-                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
-                    "flops_per_launch": flops}
+        mpeak = PEAKS["fp32_mfma"] if args.precision == "fp32" else PEAKS[f"{args.precision}_mfma"]
+        tflops = flops / sec / 1e12
+        if flops / abytes >= mpeak * 1e12 / (PEAKS["hbm_gbs"] * 1e9):
+            # above the ridge point: the contraction bounds the kernel
+            roofline = {"bound": "mfma", "kernel": dom, "achieved": round(tflops, 3), "peak": mpeak,
+                        "unit": "TFLOP/s", "frac": round(tflops / mpeak, 4), "traffic": traffic,
+                        "flops_per_launch": flops, "algorithmic_bytes_per_launch": abytes}
+        else:
+            # below it (reduced precision): the U/Q state traffic bounds the kernel
+            gbs = abytes / sec / 1e9
+            roofline = {"bound": "hbm", "kernel": dom, "achieved": round(gbs, 1), "peak": PEAKS["hbm_gbs"],
+                        "unit": "GB/s", "frac": round(gbs / PEAKS["hbm_gbs"], 4), "traffic": traffic,
+                        "algorithmic_bytes_per_launch": abytes, "flops_per_launch": flops,
+                        "mfma_tflops": round(tflops, 3), "mfma_frac": round(tflops / mpeak, 4)}
 
     if args.calibrate_copy:
         x = torch.ones(64 << 20, dtype=torch.float32, device=dev)

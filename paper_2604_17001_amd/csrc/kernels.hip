@@ -1323,31 +1323,36 @@ __global__ __launch_bounds__(kThreads) void k_colnorm_finish(StageArgs a) {
   const int kp = a.kp;
   const double* colsum = I.slice;
   const double* scal = I.slice + 2 * kp;
-  __shared__ double sh_obj[kThreads / 64], sh_max[kThreads / 64], sh_sc[2];
-  double obj = 0.0, mx = 0.0;
+  __shared__ double sh_obj[kThreads / 64], sh_max[kThreads / 64], sh_rs[kThreads / 64], sh_ds[kThreads / 64];
+  __shared__ double sh_sc[2];
+  double obj = 0.0, mx = 0.0, rs = 0.0, ds = 0.0;
   for (int c = tid; c < kp; c += kThreads) {
     obj += sqrt(colsum[2 * c + 1]);
     mx = fmax(mx, sqrt(colsum[2 * c]));
+  }
+  // slice partials of the residual sums: strided over the block, fixed tree
+  for (int j = tid; j < I.nslice; j += kThreads) {
+    rs += scal[2 * j];
+    ds += scal[2 * j + 1];
   }
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     obj += __shfl_xor(obj, o, 64);
     mx = fmax(mx, __shfl_xor(mx, o, 64));
+    rs += __shfl_xor(rs, o, 64);
+    ds += __shfl_xor(ds, o, 64);
   }
   if (lane == 0) {
     sh_obj[wave] = obj;
     sh_max[wave] = mx;
-  }
-  if (tid == 0) {
-    double rs = 0.0, ds = 0.0;
-    for (int j = 0; j < I.nslice; ++j) {
-      rs += scal[2 * j];
-      ds += scal[2 * j + 1];
-    }
-    sh_sc[0] = rs;
-    sh_sc[1] = ds;
+    sh_rs[wave] = rs;
+    sh_ds[wave] = ds;
   }
   __syncthreads();
+  if (tid == 0) {
+    sh_sc[0] = ((sh_rs[0] + sh_rs[1]) + sh_rs[2]) + sh_rs[3];
+    sh_sc[1] = ((sh_ds[0] + sh_ds[1]) + sh_ds[2]) + sh_ds[3];
+  }
   __shared__ int go_on;
   if (tid == 0) {
     const double objective = ((sh_obj[0] + sh_obj[1]) + sh_obj[2]) + sh_obj[3];

@@ -609,7 +609,6 @@ struct icnnm_ctx {
   uint64_t next_ticket = 1;
   bool stop = false;
   std::thread server;
-  hipStream_t serve_stream = nullptr;
   icnnm::Group::Prof prof;  // stage timing of synchronous calls
 };
 
@@ -994,9 +993,21 @@ icnnm_status icnnm_solve_batch(icnnm_ctx* c, int32_t count, const icnnm_shape sh
 // ================================================================================ serving
 namespace icnnm {
 
+// Requests that share V, kernel size and precision iterate in one group; each group
+// has its own stream, so groups of different kernel sizes overlap on the device.
 struct ServeGroup {
   std::unique_ptr<Group> g;
   std::vector<std::unique_ptr<Member>> active;
+  hipStream_t stream = nullptr;
+  std::vector<InstState> sts;
+  double work = 0.0;  // sum over members of m kp^2: the cost of one round
+  ServeGroup() = default;
+  ServeGroup(const ServeGroup&) = delete;
+  ServeGroup& operator=(const ServeGroup&) = delete;
+  ~ServeGroup() {
+    g.reset();
+    if (stream) (void)hipStreamDestroy(stream);
+  }
 };
 
 static std::string group_key(const float* V, const int kd[3], int prec) {
@@ -1006,7 +1017,8 @@ static std::string group_key(const float* V, const int kd[3], int prec) {
 }
 
 constexpr int kServeSlots = 512;
-constexpr int kServeRounds = 4;
+constexpr int kServeRounds = 4;      // rounds per scheduling pass of the costliest group
+constexpr int kServeMaxRounds = 64;  // ... and at most for cheaper groups
 
 // Continuous batching: admit queued requests while the HBM budget allows, run all
 // admitted requests of a (V, kernel, precision) group in joint launches, retire
@@ -1014,8 +1026,6 @@ constexpr int kServeRounds = 4;
 static void serve_loop(icnnm_ctx* c) {
   (void)hipSetDevice(c->device);
   std::map<std::string, ServeGroup> groups;
-  std::vector<InstState> sts;
-  hipStream_t st = c->serve_stream;
   for (;;) {
     std::vector<Request> admit;
     {
@@ -1037,8 +1047,9 @@ static void serve_loop(icnnm_ctx* c) {
         const std::string key = group_key(r.V, r.kd, r.params.precision);
         ServeGroup& sg = groups[key];
         if (!sg.g) {
+          HIPCK(hipStreamCreateWithFlags(&sg.stream, hipStreamNonBlocking));
           sg.g = std::make_unique<Group>(&c->budget, r.kd, r.params.precision, kServeSlots);
-          sg.g->set_v(r.V, st);
+          sg.g->set_v(r.V, sg.stream);
         }
         auto mb = std::make_unique<Member>();
         mb->plan = make_plan(r.m, r.kd, sg.g->kp);
@@ -1049,7 +1060,8 @@ static void serve_loop(icnnm_ctx* c) {
         mb->ticket = r.ticket;
         mb->t_submit = r.t_submit;
         mb->t_start = now_s();
-        sg.g->attach(mb.get(), st);
+        sg.g->attach(mb.get(), sg.stream);
+        sg.work += (double)mb->plan.mtot * sg.g->kp * sg.g->kp;
         sg.active.push_back(std::move(mb));
         return ICNNM_OK;
       });
@@ -1062,36 +1074,53 @@ static void serve_loop(icnnm_ctx* c) {
       }
     }
     for (auto it = groups.begin(); it != groups.end();) {
-      ServeGroup& sg = it->second;
-      if (sg.active.empty()) {
+      if (it->second.active.empty())
         it = groups.erase(it);
-        continue;
-      }
-      icnnm_status rc = guarded(c, [&]() -> icnnm_status {
-        sg.g->run(kServeRounds, st, true, kServeRounds);
-        sg.g->read_states(sts, st);
+      else
+        ++it;
+    }
+    // launch every group's rounds on its own stream first, then collect: groups run
+    // concurrently, and a cheaper group runs proportionally more rounds per pass so
+    // that its requests are not held back by the rounds of a costlier group
+    double wmax = 0.0;
+    for (auto& kv : groups) wmax = std::max(wmax, kv.second.work);
+    std::map<std::string, icnnm_status> rcs;
+    for (auto& kv : groups) {
+      ServeGroup& sg = kv.second;
+      const double share = sg.work > 0.0 ? wmax / sg.work : 1.0;
+      const int rounds = (int)std::min<double>(kServeMaxRounds, kServeRounds * std::max(1.0, std::floor(share)));
+      rcs[kv.first] = guarded(c, [&]() -> icnnm_status {
+        sg.g->run(rounds, sg.stream, true, kServeRounds);
+        return ICNNM_OK;
+      });
+    }
+    for (auto& kv : groups) {
+      ServeGroup& sg = kv.second;
+      icnnm_status rc = rcs[kv.first];
+      if (rc == ICNNM_OK) rc = guarded(c, [&]() -> icnnm_status {
+        sg.g->read_states(sg.sts, sg.stream);
         return ICNNM_OK;
       });
       std::vector<std::unique_ptr<Member>> keep;
       for (auto& mb : sg.active) {
-        const InstState& s = sts[mb->slot];
-        if (rc == ICNNM_OK && s.phase != kDone) {
+        const InstState* s = rc == ICNNM_OK ? &sg.sts[mb->slot] : nullptr;
+        if (s && s->phase != kDone) {
           keep.push_back(std::move(mb));
           continue;
         }
         Done d{};
-        d.status = rc != ICNNM_OK ? rc : (s.status != 0 ? ICNNM_E_NUMERIC : ICNNM_OK);
-        fill_info(s, &d.info);
+        d.status = rc != ICNNM_OK ? rc : (s->status != 0 ? ICNNM_E_NUMERIC : ICNNM_OK);
+        if (s) fill_info(*s, &d.info);
         const double t = now_s();
         d.info.t_queue_s = mb->t_start - mb->t_submit;
         d.info.t_device_s = t - mb->t_start;
+        sg.work -= (double)mb->plan.mtot * sg.g->kp * sg.g->kp;
         sg.g->detach(mb.get());
         std::lock_guard<std::mutex> lk(c->q_mu);
         c->done[mb->ticket] = d;
         c->pending.erase(mb->ticket);
       }
       sg.active = std::move(keep);
-      ++it;
     }
   }
 }
@@ -1121,10 +1150,7 @@ static icnnm_status do_submit(icnnm_ctx* c, const icnnm_shape* shape, const floa
   if (r.bytes + vbytes + sizeof(InstState) * kServeSlots > c->budget.limit)
     throw Error(ICNNM_E_BUDGET, "request alone exceeds the HBM budget");
   std::lock_guard<std::mutex> lk(c->q_mu);
-  if (!c->server.joinable()) {
-    HIPCK(hipStreamCreateWithFlags(&c->serve_stream, hipStreamNonBlocking));
-    c->server = std::thread(serve_loop, c);
-  }
+  if (!c->server.joinable()) c->server = std::thread(serve_loop, c);
   r.ticket = c->next_ticket++;
   c->pending[r.ticket] = 1;
   c->queue.push_back(r);
@@ -1196,7 +1222,6 @@ void icnnm_destroy(icnnm_ctx* c) {
     for (auto& e : c->prof.ev) (void)hipEventDestroy(e);
     c->prof.ev.clear();
   }
-  if (c->serve_stream) (void)hipStreamDestroy(c->serve_stream);
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ev_out) (void)hipEventDestroy(c->ev_out);
   if (c->stream) (void)hipStreamDestroy(c->stream);

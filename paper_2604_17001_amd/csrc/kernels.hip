@@ -958,64 +958,71 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big(StageArgs a) {
   gcfloat4* Q4 = gc4(I.Q);
   const int rg = tid >> 6, hf = (tid >> 5) & 1;
   const float* vrow = a.Vp + (size_t)(sg * kGroup + tid) * kp;
-  float4 cu[2], cq[2], cs[2], cv[4];
-  auto coop_load = [&](int q) {
+  // two register slots: the loads of chunk q + 2 are issued while chunk q is
+  // contracted, so each chunk's global loads have two contraction phases to land
+  float4 cu[2][2], cq[2][2], cs[2][2], cv[2][4];  // [slot][...]
+  auto coop_load = [&](int q, int sl) {
     const int cb = q >> 1, p = q & 1;
     const size_t o = (((size_t)lt * 4 + rg) * nkb + cb) * 256 + lane * 4 + 2 * p;
-    cu[0] = U4[o];
-    cu[1] = U4[o + 1];
-    cq[0] = Q4[o];
-    cq[1] = Q4[o + 1];
-    cs[0] = *gc4(I.s + cb * 32 + (2 * p) * 8 + hf * 4);
-    cs[1] = *gc4(I.s + cb * 32 + (2 * p + 1) * 8 + hf * 4);
+    cu[sl][0] = U4[o];
+    cu[sl][1] = U4[o + 1];
+    cq[sl][0] = Q4[o];
+    cq[sl][1] = Q4[o + 1];
+    cs[sl][0] = *gc4(I.s + cb * 32 + (2 * p) * 8 + hf * 4);
+    cs[sl][1] = *gc4(I.s + cb * 32 + (2 * p + 1) * 8 + hf * 4);
     gcfloat4* vp = gc4(vrow + q * kBigChunk);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) cv[i] = vp[i];
+    for (int i = 0; i < 4; ++i) cv[sl][i] = vp[i];
   };
-  auto coop_store = [&](int buf) {
+  auto coop_store = [&](int buf, int sl) {
     // G values of v = 8p..8p+7 sit at chunk columns (v%8/4)*8 + hf*4 + v%4
     float* gd = Gs + ((size_t)buf * 128 + rg * 32 + (lane & 31)) * kBigPad + hf * 4;
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      gd[8 * t + 0] = cu[t].x + cs[t].x * cq[t].x;
-      gd[8 * t + 1] = cu[t].y + cs[t].y * cq[t].y;
-      gd[8 * t + 2] = cu[t].z + cs[t].z * cq[t].z;
-      gd[8 * t + 3] = cu[t].w + cs[t].w * cq[t].w;
+      gd[8 * t + 0] = cu[sl][t].x + cs[sl][t].x * cq[sl][t].x;
+      gd[8 * t + 1] = cu[sl][t].y + cs[sl][t].y * cq[sl][t].y;
+      gd[8 * t + 2] = cu[sl][t].z + cs[sl][t].z * cq[sl][t].z;
+      gd[8 * t + 3] = cu[sl][t].w + cs[sl][t].w * cq[sl][t].w;
     }
     float* vd = Vs + ((size_t)buf * 256 + tid) * kBigPad;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      vd[4 * i + 0] = cv[i].x;
-      vd[4 * i + 1] = cv[i].y;
-      vd[4 * i + 2] = cv[i].z;
-      vd[4 * i + 3] = cv[i].w;
+      vd[4 * i + 0] = cv[sl][i].x;
+      vd[4 * i + 1] = cv[sl][i].y;
+      vd[4 * i + 2] = cv[sl][i].z;
+      vd[4 * i + 3] = cv[sl][i].w;
     }
   };
-  const int nq = kp / kBigChunk;
-  coop_load(0);
-  coop_store(0);
+  const int nq = kp / kBigChunk;  // even (kp is a multiple of 256)
+  coop_load(0, 0);
+  coop_load(1, 1);
+  coop_store(0, 0);
   __syncthreads();
-  for (int q = 0; q < nq; ++q) {
-    const int buf = q & 1;
-    if (q + 1 < nq) coop_load(q + 1);
-    const float* gb = Gs + ((size_t)buf * 128 + rw * 64 + (lane & 31)) * kBigPad + half;
-    const float* vb = Vs + ((size_t)buf * 256 + sh * 128 + (lane & 31)) * kBigPad + half;
+  for (int q0 = 0; q0 < nq; q0 += 2) {
 #pragma unroll
-    for (int kk = 0; kk < kBigChunk / 2; ++kk) {
-      const float g0 = gb[2 * kk], g1 = gb[32 * kBigPad + 2 * kk];
-      float v[4];
+    for (int sl = 0; sl < 2; ++sl) {
+      const int q = q0 + sl;
+      // slot sl held chunk q, already in LDS: refill it with chunk q + 2 (clamped, so
+      // the body stays branch-free; the last chunks reload harmlessly)
+      coop_load(min(q + 2, nq - 1), sl);
+      const float* gb = Gs + ((size_t)sl * 128 + rw * 64 + (lane & 31)) * kBigPad + half;
+      const float* vb = Vs + ((size_t)sl * 256 + sh * 128 + (lane & 31)) * kBigPad + half;
 #pragma unroll
-      for (int sb = 0; sb < 4; ++sb) v[sb] = vb[sb * 32 * kBigPad + 2 * kk];
+      for (int kk = 0; kk < kBigChunk / 2; ++kk) {
+        const float g0 = gb[2 * kk], g1 = gb[32 * kBigPad + 2 * kk];
+        float v[4];
 #pragma unroll
-      for (int sb = 0; sb < 4; ++sb) {
-        acc[sb][0] = mfma32(v[sb], g0, acc[sb][0]);
-        acc[sb][1] = mfma32(v[sb], g1, acc[sb][1]);
+        for (int sb = 0; sb < 4; ++sb) v[sb] = vb[sb * 32 * kBigPad + 2 * kk];
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb) {
+          acc[sb][0] = mfma32(v[sb], g0, acc[sb][0]);
+          acc[sb][1] = mfma32(v[sb], g1, acc[sb][1]);
+        }
       }
+      if (q + 1 < nq) coop_store(sl ^ 1, sl ^ 1);
+      __syncthreads();
     }
-    if (q + 1 < nq) coop_store(buf ^ 1);
-    __syncthreads();
   }
-  // col2im in two rounds of 128 offsets: the wavefronts of offset half `rd` stage
   const int hstride = 128 + 4;
   float* Hs = smem;
   for (int rd = 0; rd < 2; ++rd) {

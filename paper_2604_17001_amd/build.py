@@ -58,7 +58,22 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    _build_c_example()
     return LIB
+
+
+def _build_c_example() -> str:
+    """Plain-C client of the C ABI (examples/solve_c.c): gcc, HIP runtime API only."""
+    src = os.path.join(HERE, "examples", "solve_c.c")
+    exe = os.path.join(HERE, "examples", "solve_c")
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(_hipcc())))
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(rocm, "include"),
+           "-I", os.path.join(ROOT, "include"), src, "-L", HERE, "-licnnm", "-L", os.path.join(rocm, "lib"),
+           "-lamdhip64", "-Wl,-rpath,$ORIGIN/..:" + os.path.join(rocm, "lib"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"C example build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return exe
 
 
 if __name__ == "__main__":

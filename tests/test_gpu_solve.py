@@ -163,3 +163,17 @@ def test_invalid_arguments_rejected(lib):
     with pytest.raises(IcnnmError):
         lib.solve(_dev(prob.M), _dev(prob.mask), _dev(bad), prob.kdims, max_iter=1, check_v=True)
     L, _ = lib.solve(_dev(prob.M), _dev(prob.mask), _dev(V32), prob.kdims, max_iter=1, check_v=True)
+
+
+def test_nan_input_reports_numeric_error(lib):
+    # a NaN among the observed entries makes the residuals non-finite: the solve stops
+    # and reports ICNNM_E_NUMERIC instead of returning a silently wrong result
+    from paper_2604_17001_amd import icnnm
+    prob, V32 = _case((12, 10, 8), (3, 3, 2), 0.4, 12)
+    obs = np.flatnonzero(prob.mask.reshape(-1))
+    M = prob.M.copy()
+    M.reshape(-1)[obs[0]] = np.nan
+    print("[gpu] nan input", flush=True)
+    with pytest.raises(icnnm.IcnnmError) as e:
+        lib.solve(_dev(M), _dev(prob.mask), _dev(V32), prob.kdims, max_iter=10)
+    assert e.value.code == icnnm.E_NUMERIC

@@ -33,7 +33,8 @@ def _projector_check(Vg, w, Vo, wo, gap=1e-6):
 
 
 @pytest.mark.parametrize("dims,kdims,b", [((12, 10, 8), (3, 3, 2), 5), ((16, 16, 8), (8, 8, 4), 20),
-                                          ((30, 20), (6, 5), 4), ((40,), (7,), 3)])
+                                          ((30, 20), (6, 5), 4), ((40,), (7,), 3),
+                                          ((64, 64), (43, 43), 2)])  # k = 1849: threaded host eigensolver
 def test_learn_matches_oracle(lib, dims, kdims, b):
     refs = inputs.random_refs(dims, b, seed=31)
     print(f"[gpu] learn dims={dims} kdims={kdims} b={b}", flush=True)

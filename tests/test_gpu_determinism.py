@@ -50,3 +50,35 @@ def test_batch_member_equals_alone_bitwise(lib, prec):
     for p, Lb in zip(probs, Ls):
         La, _ = lib.solve(_dev(p.M), _dev(p.mask), _dev(V32), kd, max_iter=30, precision=prec)
         assert np.array_equal(Lb.cpu().numpy(), La.cpu().numpy())
+
+
+def test_concurrent_host_threads_on_one_context(lib):
+    # calls on one context from several host threads are serialised by the library;
+    # each thread's results equal the sequential ones bit for bit
+    import threading
+    kd = (4, 4, 2)
+    probs = [inputs.random_problem((16, 12, 8), kd, 0.4, 60 + i) for i in range(4)]
+    V, _ = O.learn(inputs.random_refs((16, 12, 8), 3, 60), kd)
+    V32 = V.astype(np.float32)
+    ref = [lib.solve(_dev(p.M), _dev(p.mask), _dev(V32), kd, max_iter=25)[0].cpu().numpy() for p in probs]
+    out = [None] * len(probs)
+    errs = []
+
+    def run(i):
+        try:
+            import torch
+            torch.cuda.set_device(0)
+            for _ in range(2):
+                out[i] = lib.solve(_dev(probs[i].M), _dev(probs[i].mask), _dev(V32), kd, max_iter=25)[0].cpu().numpy()
+        except Exception as e:  # pragma: no cover - reported below
+            errs.append(e)
+
+    print("[gpu] concurrent host threads", flush=True)
+    ts = [threading.Thread(target=run, args=(i,)) for i in range(len(probs))]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert not errs, errs
+    for a, b in zip(out, ref):
+        assert np.array_equal(a, b)

@@ -33,10 +33,10 @@ METRIC = "solved tensors/s at rel.err\u22641e-3 vs FP64 oracle; p50/p99 latency;
 # the same counters on a plain 256 MiB copy (fetch x2.0, write x1.0); valid only for the
 # kernel source they were taken on (sha256 prefix of kernels.hip)
 TRAFFIC = {
-    ("c2", "fp32", "forward"): {"bytes": 291.0e6, "src": "8392d467a369d7dc"},
-    ("c2", "fp32", "adjoint"): {"bytes": 139.4e6, "src": "8392d467a369d7dc"},
-    ("c3", "bf16", "forward"): {"bytes": 10.17e9, "src": "8392d467a369d7dc"},
-    ("c3", "bf16", "adjoint"): {"bytes": 5.64e9, "src": "8392d467a369d7dc"},
+    ("64x64x16", "fp32", "forward"): {"bytes": 291.0e6, "src": "8392d467a369d7dc"},
+    ("64x64x16", "fp32", "adjoint"): {"bytes": 139.4e6, "src": "8392d467a369d7dc"},
+    ("128x128x32", "bf16", "forward"): {"bytes": 10.17e9, "src": "8392d467a369d7dc"},
+    ("128x128x32", "bf16", "adjoint"): {"bytes": 5.64e9, "src": "8392d467a369d7dc"},
 }
 
 
@@ -48,7 +48,8 @@ def _kernel_src_hash():
 
 def _workload(name):
     from paper_2604_17001_amd import inputs
-    return {"c1": inputs.c1_plain, "c2": inputs.c2_plain, "c3": inputs.c3_precision, "c4": inputs.c4_batch}[name]()
+    return {"16x16x8": inputs.prediction_16x16x8, "64x64x16": inputs.video_64x64x16,
+            "128x128x32": inputs.interpolation_128x128x32, "batch": inputs.batch_uneven}[name]()
 
 
 def _batch_main(args):
@@ -56,7 +57,7 @@ def _batch_main(args):
     one shared V) solved in joint launches; a step is one solve of the whole batch."""
     import torch
     from paper_2604_17001_amd import icnnm
-    wl = _workload("c4")
+    wl = _workload("batch")
     iters = args.iters or wl.iters
     lib = icnnm.Library.get()
     dev = torch.device("cuda", 0)
@@ -111,7 +112,7 @@ def _serve_main(args):
     lib = icnnm.Library(budget=int(args.budget_gb * (1 << 30)))
     dev = torch.device("cuda", 0)
     banks = {}
-    for kd, gen in [((8, 8, 4), inputs.c4_batch), ((16, 16, 4), inputs.c3_precision)]:
+    for kd, gen in [((8, 8, 4), inputs.batch_uneven), ((16, 16, 4), inputs.interpolation_128x128x32)]:
         if any(tuple(p.kdims) == kd for p in probs):
             refs = gen(b_refs=4).refs if kd == (16, 16, 4) else gen(count=1).refs
             banks[kd] = lib.learn_eigvecs([torch.from_numpy(r).to(dev) for r in refs], kd)[0]
@@ -144,7 +145,7 @@ def _serve_main(args):
            "unit": "tensors/s", "n_gpus": 1, "steps": n, "warmup": 0, "ms_per_step": round(1e3 * total / n, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.precision,
            "data": "synthetic",
-           "config": {"workload": "c5_serve_poisson", "rate_req_s": rate, "requests": n,
+           "config": {"workload": "serve_poisson_mixed_sizes", "rate_req_s": rate, "requests": n,
                       "large_frac": args.large_frac, "tol": args.tol, "budget_gb": args.budget_gb},
            "p50_ms": round(float(np.percentile(lat_ms, 50)), 2), "p99_ms": round(float(np.percentile(lat_ms, 99)), 2),
            "ok": int(sum(1 for v in done.values() if v == icnnm.OK)), "mean_iters": round(float(np.mean(iters)), 1)}
@@ -172,12 +173,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
-    ap.add_argument("--rate", type=float, default=10.0, help="c5: Poisson arrival rate (req/s)")
-    ap.add_argument("--requests", type=int, default=64, help="c5: number of requests")
-    ap.add_argument("--large-frac", type=float, default=0.10, help="c5: share of 128x128x32 requests")
-    ap.add_argument("--tol", type=float, default=1e-4, help="c5: retirement residual")
-    ap.add_argument("--budget-gb", type=float, default=200.0, help="c5: HBM budget of the server")
+    ap.add_argument("--workload", default="64x64x16", choices=["16x16x8", "64x64x16", "128x128x32", "batch", "serve"],
+                    help="16x16x8 prediction, 64x64x16 video (default), 128x128x32 interpolation at k=1024, "
+                         "64-instance uneven batch, serving with Poisson arrivals")
+    ap.add_argument("--rate", type=float, default=10.0, help="serve: Poisson arrival rate (req/s)")
+    ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
+    ap.add_argument("--large-frac", type=float, default=0.10, help="serve: share of 128x128x32 requests")
+    ap.add_argument("--tol", type=float, default=1e-4, help="serve: retirement residual")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: HBM budget of the server")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--cpu-sample-iters", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -193,9 +196,9 @@ def main():
               "independent instances shard across GPUs without communication", file=sys.stderr)
         sys.exit(2)
 
-    if args.workload == "c4":
+    if args.workload == "batch":
         return _batch_main(args)
-    if args.workload == "c5":
+    if args.workload == "serve":
         return _serve_main(args)
 
     import torch
@@ -289,7 +292,7 @@ def main():
     # the same workload in the other form (BF16 against plain FP32 or the reverse), with
     # its own accuracy against the stored oracle result, for the "vs plain FP32" figure
     other = None
-    if not args.no_compare and args.workload in ("c1", "c2", "c3") and args.iters == 0:
+    if not args.no_compare and args.workload in ("16x16x8", "64x64x16", "128x128x32") and args.iters == 0:
         oprec = "bf16" if args.precision == "fp32" else "fp32"
         okw = dict(max_iter=wl.iters, precision=oprec)
         for _ in range(args.warmup):

@@ -142,41 +142,41 @@ def _refs(cfg, gen_one, b):
     return [gen_one(rng(cfg, ROLE_REFS, j)) for j in range(b)]
 
 
-def c1_plain(b_refs=20) -> Workload:
+def prediction_16x16x8(b_refs=20) -> Workload:
     """16x16x8 tensor, 8x8x4 kernel, r=5 separable cosines + N(0,1e-3);
     frames 1-6 observed, 7-8 missing (prediction); 100 iterations."""
     dims, kd = (16, 16, 8), (8, 8, 4)
     gen = lambda g: cosine_sum(dims, 5, g, sigma=1e-3, separable=True)
     M = gen(rng(1, ROLE_TARGET))
     mask = mask_trailing_missing(dims, 2)
-    return Workload("c1_plain_16x16x8_k8x8x4", kd, [Problem(dims, kd, M, mask, "c1")],
+    return Workload("prediction_16x16x8_k8x8x4", kd, [Problem(dims, kd, M, mask, "16x16x8")],
                     _refs(1, gen, b_refs), 100)
 
 
-def c2_plain(b_refs=20) -> Workload:
+def video_64x64x16(b_refs=20) -> Workload:
     """64x64x16 tensor, 8x8x4 kernel, r=12 cosines + N(0,1e-2), scaled to [0,1];
     30% random missing plus 8x8x1 missing blocks over 15% of the volume; 200 it."""
     dims, kd = (64, 64, 16), (8, 8, 4)
     gen = lambda g: cosine_sum(dims, 12, g, sigma=1e-2, scale01=True)
     M = gen(rng(2, ROLE_TARGET))
     mask = mask_random_plus_blocks(dims, 0.30, (8, 8, 1), 0.15, rng(2, ROLE_MASK))
-    return Workload("c2_plain_64x64x16_k8x8x4", kd, [Problem(dims, kd, M, mask, "c2")],
+    return Workload("video_64x64x16_k8x8x4", kd, [Problem(dims, kd, M, mask, "64x64x16")],
                     _refs(2, gen, b_refs), 200)
 
 
-def c3_precision(b_refs=20) -> Workload:
+def interpolation_128x128x32(b_refs=20) -> Workload:
     """128x128x32 tensor, 16x16x4 kernel, r=20 cosines + N(0,1e-2), scaled [0,1];
     even frames observed (frame interpolation); 100 iterations."""
     dims, kd = (128, 128, 32), (16, 16, 4)
     gen = lambda g: cosine_sum(dims, 20, g, sigma=1e-2, scale01=True)
     M = gen(rng(3, ROLE_TARGET))
     mask = mask_every_other_frame(dims)
-    return Workload("c3_precision_128x128x32_k16x16x4", kd, [Problem(dims, kd, M, mask, "c3")],
+    return Workload("interpolation_128x128x32_k16x16x4", kd, [Problem(dims, kd, M, mask, "128x128x32")],
                     _refs(3, gen, b_refs), 100)
 
 
-C4_SPATIAL = (32, 48, 64, 96, 128)
-C4_FRAMES = (8, 16, 32)
+BATCH_SPATIAL = (32, 48, 64, 96, 128)
+BATCH_FRAMES = (8, 16, 32)
 
 
 def batch_instance(cfg, idx, kdims=(8, 8, 4)) -> Problem:
@@ -184,7 +184,7 @@ def batch_instance(cfg, idx, kdims=(8, 8, 4)) -> Problem:
     values as the 64x64x16 generator; the mask is one of three types drawn uniformly:
     40% random missing / last ceil(m3/4) frames missing / odd frames missing."""
     g = rng(cfg, ROLE_TARGET, idx)
-    dims = (int(g.choice(C4_SPATIAL)), int(g.choice(C4_SPATIAL)), int(g.choice(C4_FRAMES)))
+    dims = (int(g.choice(BATCH_SPATIAL)), int(g.choice(BATCH_SPATIAL)), int(g.choice(BATCH_FRAMES)))
     M = cosine_sum(dims, 12, g, sigma=1e-2, scale01=True)
     gm = rng(cfg, ROLE_MASK, idx)
     kind = int(gm.integers(0, 3))
@@ -194,17 +194,17 @@ def batch_instance(cfg, idx, kdims=(8, 8, 4)) -> Problem:
         mask = mask_trailing_missing(dims, int(math.ceil(dims[2] / 4)))
     else:
         mask = mask_every_other_frame(dims)
-    return Problem(dims, tuple(kdims), M, mask, f"c{cfg}_{idx}", {"mask_kind": kind})
+    return Problem(dims, tuple(kdims), M, mask, f"batch_{idx}", {"mask_kind": kind})
 
 
-def c4_batch(count=64, b_refs=20) -> Workload:
+def batch_uneven(count=64, b_refs=20) -> Workload:
     kd = (8, 8, 4)
     probs = [batch_instance(4, i, kd) for i in range(count)]
 
     def ref(g):
-        dims = (int(g.choice(C4_SPATIAL)), int(g.choice(C4_SPATIAL)), int(g.choice(C4_FRAMES)))
+        dims = (int(g.choice(BATCH_SPATIAL)), int(g.choice(BATCH_SPATIAL)), int(g.choice(BATCH_FRAMES)))
         return cosine_sum(dims, 12, g, sigma=1e-2, scale01=True)
-    return Workload("c4_batch_64_uneven_k8x8x4", kd, probs, _refs(4, ref, b_refs), 200)
+    return Workload("batch_64_uneven_k8x8x4", kd, probs, _refs(4, ref, b_refs), 200)
 
 
 def serve_requests(n, rate, large_frac=0.10, cfg=5):

@@ -10,7 +10,7 @@ generators; nothing here touches the GPU library. For each workload it stores
   (float64), computed from the float32 inputs upcast to float64;
 * ``<name>_meta.json`` - iterations, theta0, residuals, objective, timings.
 
-Usage: python tests/golden/make_golden.py c1 c2 [c3]
+Usage: python tests/golden/make_golden.py 16x16x8 64x64x16 [128x128x32]
 """
 import json
 import os
@@ -26,7 +26,8 @@ from oracle import icnnm_ref as O  # noqa: E402
 from paper_2604_17001_amd import inputs  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-WORKLOADS = {"c1": inputs.c1_plain, "c2": inputs.c2_plain, "c3": inputs.c3_precision}
+WORKLOADS = {"16x16x8": inputs.prediction_16x16x8, "64x64x16": inputs.video_64x64x16,
+             "128x128x32": inputs.interpolation_128x128x32}
 
 
 def make(name):
@@ -50,5 +51,5 @@ def make(name):
 
 
 if __name__ == "__main__":
-    for n in sys.argv[1:] or ["c1", "c2"]:
+    for n in sys.argv[1:] or ["16x16x8", "64x64x16"]:
         make(n)

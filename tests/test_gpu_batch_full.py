@@ -19,7 +19,7 @@ def _dev(x):
 
 @pytest.mark.parametrize("prec,tol_oracle,tol_alone", [("fp32", 1e-5, 1e-6), ("bf16", 1e-3, 1e-5)])
 def test_full_batch(lib, prec, tol_oracle, tol_alone):
-    wl = inputs.c4_batch(b_refs=4)
+    wl = inputs.batch_uneven(b_refs=4)
     iters = 100
     V, _ = O.learn(wl.refs[:2], wl.kdims)
     V32 = V.astype(np.float32)

@@ -18,8 +18,8 @@ def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).cuda()
 
 
-@pytest.mark.parametrize("name,factory", [("c1", inputs.c1_plain), ("c2", inputs.c2_plain),
-                                          ("c3", inputs.c3_precision)])
+@pytest.mark.parametrize("name,factory", [("16x16x8", inputs.prediction_16x16x8), ("64x64x16", inputs.video_64x64x16),
+                                          ("128x128x32", inputs.interpolation_128x128x32)])
 def test_config_matches_stored_oracle(lib, name, factory):
     if not os.path.exists(os.path.join(GOLD, f"{name}_L.npy")):
         pytest.skip("stored oracle result missing")

@@ -81,8 +81,8 @@ def test_precision_needs_innermost_kernel_multiple_of_4(lib):
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
-@pytest.mark.parametrize("name,factory", [("c1", inputs.c1_plain), ("c2", inputs.c2_plain),
-                                          ("c3", inputs.c3_precision)])
+@pytest.mark.parametrize("name,factory", [("16x16x8", inputs.prediction_16x16x8), ("64x64x16", inputs.video_64x64x16),
+                                          ("128x128x32", inputs.interpolation_128x128x32)])
 def test_config_reduced_precision_vs_stored_oracle(lib, prec, name, factory):
     if not os.path.exists(os.path.join(GOLD, f"{name}_L.npy")):
         pytest.skip("stored oracle result missing")

@@ -276,8 +276,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   const int E123 = I.E123;
   const int E12 = I.E[1] * I.E[2];
   const int nrc = I.bm / kRowUnit, ncc = CG / kColUnit;
-  // FP32: halo of L (E123 floats) + offset table offs2[h*16 + half*8 + jj] = off(s),
-  //       s = (h/2)*32 + (h%2)*16 + 2*jj + half
+  // FP32: halo of L (E123 floats) + offset table offs2[h*16 + half*8 + jj] = -4 off(s)
+  //       (a byte offset), s = (h/2)*32 + (h%2)*16 + 2*jj + half
   // reduced precision: halo of D = L^t - L^{t-1} expanded along the innermost
   //       dimension, E4[y][d] = D_halo[y - d] (d < 4), so one 8-byte read yields four
   //       consecutive kernel offsets; offset table offs4[kk*4 + half*2 + g] = off(s)
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
     }
     for (int e = tid; e < kp; e += kThreads) {
       const int h = e >> 4, hf = (e >> 3) & 1, jj = e & 7;
-      offs2[e] = kernel_off((h >> 1) * 32 + (h & 1) * 16 + 2 * jj + hf, I, k);
+      offs2[e] = -4 * kernel_off((h >> 1) * 32 + (h & 1) * 16 + 2 * jj + hf, I, k);
     }
   } else {
     typedef typename LowP<MODE>::h H;
@@ -375,48 +375,71 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
 
     if constexpr (MODE == kFP32) {
     // V fragments: per (column block, offset block) 16 floats per lane in k-step
-    // order, consumed in halves of 8 k-steps. Each iteration first takes the
-    // operands loaded during the previous one, then issues the loads of the next
-    // half-step, then runs its 32 MFMAs, so the loads overlap the MFMAs.
+    // order, consumed in half-steps of 8 k-steps (32 MFMAs). The loop is unrolled by
+    // two with ping-pong operand registers: each half-step first issues the V loads
+    // and halo reads of the next one and the offset-table read of the one after, then
+    // runs its MFMAs on operands fetched a half-step earlier. A halo read costs one
+    // add: lane byte address of the row block plus the pre-scaled table entry.
     gcfloat4* vf0 = gc4(a.Vf) + (size_t)(c0 / 32) * nkb * 256 + lane * 4;
-    gcfloat4* vf1 = vf0 + (size_t)nkb * 256;
-    float4 vn[2][2];
-    float bn[2][8];
-    auto load_half = [&](int h) {
+    const size_t vstride = (size_t)nkb * 256;
+    const char* hb = reinterpret_cast<const char*>(halo);
+    const int rb0 = 4 * base[0], rb1 = 4 * base[1];
+    const int* tp = offs2 + half * 8;
+    float4 va[2][4];
+    float bv[2][2][8];
+    int4 tb0, tb1;
+    auto fetch_v = [&](int h, float4 (&d)[4]) {
       const size_t q = (size_t)(h >> 1) * 256 + (h & 1) * 2;
-      vn[0][0] = vf0[q];
-      vn[0][1] = vf0[q + 1];
-      vn[1][0] = vf1[q];
-      vn[1][1] = vf1[q + 1];
-      const int4* ot = reinterpret_cast<const int4*>(offs2 + h * 16 + half * 8);
-      const int4 oa = ot[0], ob = ot[1];
-      const int ov[8] = {oa.x, oa.y, oa.z, oa.w, ob.x, ob.y, ob.z, ob.w};
+      d[0] = vf0[q];
+      d[1] = vf0[q + 1];
+      d[2] = vf0[vstride + q];
+      d[3] = vf0[vstride + q + 1];
+    };
+    auto fetch_t = [&](int h) {
+      const int4* t = reinterpret_cast<const int4*>(tp + h * 16);
+      tb0 = t[0];
+      tb1 = t[1];
+    };
+    auto fetch_b = [&](float (&d)[2][8]) {
+      const int ov[8] = {tb0.x, tb0.y, tb0.z, tb0.w, tb1.x, tb1.y, tb1.z, tb1.w};
 #pragma unroll
       for (int jj = 0; jj < 8; ++jj) {
-        bn[0][jj] = halo[base[0] - ov[jj]];
-        bn[1][jj] = halo[base[1] - ov[jj]];
+        d[0][jj] = *reinterpret_cast<const float*>(hb + (rb0 + ov[jj]));
+        d[1][jj] = *reinterpret_cast<const float*>(hb + (rb1 + ov[jj]));
       }
     };
-    load_half(0);
-    for (int h = 0; h < nhs; ++h) {
-      const float a0[8] = {vn[0][0].x, vn[0][0].y, vn[0][0].z, vn[0][0].w,
-                           vn[0][1].x, vn[0][1].y, vn[0][1].z, vn[0][1].w};
-      const float a1[8] = {vn[1][0].x, vn[1][0].y, vn[1][0].z, vn[1][0].w,
-                           vn[1][1].x, vn[1][1].y, vn[1][1].z, vn[1][1].w};
-      float b0[8], b1[8];
+    auto mfma_half = [&](const float4 (&v)[4], const float (&b)[2][8]) {
+      const float a0[8] = {v[0].x, v[0].y, v[0].z, v[0].w, v[1].x, v[1].y, v[1].z, v[1].w};
+      const float a1[8] = {v[2].x, v[2].y, v[2].z, v[2].w, v[3].x, v[3].y, v[3].z, v[3].w};
 #pragma unroll
       for (int jj = 0; jj < 8; ++jj) {
-        b0[jj] = bn[0][jj];
-        b1[jj] = bn[1][jj];
+        acc[0][0] = mfma32(a0[jj], b[0][jj], acc[0][0]);
+        acc[0][1] = mfma32(a0[jj], b[1][jj], acc[0][1]);
+        acc[1][0] = mfma32(a1[jj], b[0][jj], acc[1][0]);
+        acc[1][1] = mfma32(a1[jj], b[1][jj], acc[1][1]);
       }
-      if (h + 1 < nhs) load_half(h + 1);
-#pragma unroll
-      for (int jj = 0; jj < 8; ++jj) {
-        acc[0][0] = mfma32(a0[jj], b0[jj], acc[0][0]);
-        acc[0][1] = mfma32(a0[jj], b1[jj], acc[0][1]);
-        acc[1][0] = mfma32(a1[jj], b0[jj], acc[1][0]);
-        acc[1][1] = mfma32(a1[jj], b1[jj], acc[1][1]);
-      }
+    };
+    // nhs is even (kp is a multiple of 64); fetches past the last half-step are
+    // clamped to it, which keeps the body branch-free
+    fetch_t(0);
+    fetch_b(bv[0]);
+    fetch_v(0, va[0]);
+    fetch_t(1);
+    // (the scheduling barriers keep the compiler from sinking the fetches below the
+    // MFMAs that do not depend on them)
+    for (int h = 0; h < nhs; h += 2) {
+      fetch_v(h + 1, va[1]);
+      fetch_b(bv[1]);
+      fetch_t(min(h + 2, nhs - 1));
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_half(va[0], bv[0]);
+      __builtin_amdgcn_sched_barrier(0);
+      fetch_v(min(h + 2, nhs - 1), va[0]);
+      fetch_b(bv[0]);
+      fetch_t(min(h + 3, nhs - 1));
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_half(va[1], bv[1]);
+      __builtin_amdgcn_sched_barrier(0);
     }
     } else {
     // reduced precision: one MFMA per (column block, row block) and 16 kernel offsets;
@@ -499,87 +522,99 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
         bq[slot][g] = Qp[g];
       }
     };
-    if (!init) {
+    // Two compiled forms of the same arithmetic: the first forward of a solve (U = 0,
+    // Q = W, nothing loaded) and every later one. Rows past the tensor's end get
+    // W = 0; their U and Q are zero from the first forward on, so every value
+    // derived from them is zero as well without further masking.
+    auto epilogue = [&](auto init_c) {
+      constexpr bool kFirst = decltype(init_c)::value;
+      if constexpr (!kFirst) {
 #pragma unroll
-      for (int i = 0; i < kAhead; ++i) load_piece(i, i);
-    }
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-      const int cblk = c0 / 32 + cb;
-      float4 s4[4];
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        s4[g] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (!init) s4[g] = *gc4(I.s + cblk * 32 + g * 8 + half * 4);
+        for (int i = 0; i < kAhead; ++i) load_piece(i, i);
       }
-      float qs[16], ws[16];
 #pragma unroll
-      for (int v = 0; v < 16; ++v) qs[v] = ws[v] = 0.f;
-#pragma unroll
-      for (int ib = 0; ib < RB; ++ib) {
-        const int pc = cb * RB + ib, slot = pc % kAhead;
-        float4 u4s[4], q4s[4];
+      for (int cb = 0; cb < 2; ++cb) {
+        const int cblk = c0 / 32 + cb;
+        float4 s4[4];
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-          u4s[g] = make_float4(0.f, 0.f, 0.f, 0.f);
-          q4s[g] = u4s[g];
-          if (!init) {
-            u4s[g] = bu[slot][g];
-            q4s[g] = bq[slot][g];
-          }
+          s4[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+          if constexpr (!kFirst) s4[g] = *gc4(I.s + cblk * 32 + g * 8 + half * 4);
         }
-        if (!init && pc + kAhead < kPieces) load_piece(pc + kAhead, slot);
-        const size_t sidx = ((((size_t)lt * (I.bm / 32) + ru * RB + ib) * nkb + cblk) * 64 + lane) * 4;
-        gfloat4* Up = g4(I.U) + sidx;
-        gfloat4* Qp = g4(I.Q) + sidx;
+        float qs[16], ws[16];
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const float4 u4 = u4s[g], q4 = q4s[g], sv4 = s4[g];
-          const float uo[4] = {u4.x, u4.y, u4.z, u4.w}, qo[4] = {q4.x, q4.y, q4.z, q4.w};
-          const float sv[4] = {sv4.x, sv4.y, sv4.z, sv4.w};
-          float un[4], qn[4];
+        for (int v = 0; v < 16; ++v) qs[v] = ws[v] = 0.f;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            float w = acc[cb][ib][4 * g + e];
-            if (MODE != kFP32) w += uo[e] + qo[e];  // W^t = W^{t-1} + A_k(L^t - L^{t-1}) V
-            float unew, qnew;
-            if (!valid[ib]) {
-              w = 0.f;
-              unew = 0.f;
-              qnew = 0.f;
-            } else if (init) {
-              unew = 0.f;
-              qnew = w;
-            } else {
-              const float z = sv[e] * qo[e];
-              const float gg = uo[e] + z;
-              unew = (gg - w) * ratio;
-              qnew = w - unew;
-              const float d = z - w;
-              rsum[ib / 2] += d * d;
+        for (int ib = 0; ib < RB; ++ib) {
+          const int pc = cb * RB + ib, slot = pc % kAhead;
+          float4 u4s[4], q4s[4];
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            u4s[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+            q4s[g] = u4s[g];
+            if constexpr (!kFirst) {
+              u4s[g] = bu[slot][g];
+              q4s[g] = bq[slot][g];
             }
-            un[e] = unew;
-            qn[e] = qnew;
-            qs[4 * g + e] += qnew * qnew;
-            ws[4 * g + e] += w * w;
           }
-          Up[g] = make_float4(un[0], un[1], un[2], un[3]);
-          Qp[g] = make_float4(qn[0], qn[1], qn[2], qn[3]);
-        }
-        if (ib & 1) {  // column partials of one 64-row chunk
-          int vi;
-          const float q = half_sum16(qs, lane, vi);
-          const float w = half_sum16(ws, lane, vi);
-          if ((lane & 1) == 0) {
-            const int col = cc * kColUnit + cb * 32 + acc_col(vi, half);
-            const int rc = ru * kRpu + ib / 2;
-            colq[rc * CG + col] = q;
-            colw[rc * CG + col] = w;
+          if constexpr (!kFirst) {
+            if (pc + kAhead < kPieces) load_piece(pc + kAhead, slot);
           }
+          const size_t sidx = ((((size_t)lt * (I.bm / 32) + ru * RB + ib) * nkb + cblk) * 64 + lane) * 4;
+          gfloat4* Up = g4(I.U) + sidx;
+          gfloat4* Qp = g4(I.Q) + sidx;
 #pragma unroll
-          for (int v = 0; v < 16; ++v) qs[v] = ws[v] = 0.f;
+          for (int g = 0; g < 4; ++g) {
+            const float4 u4 = u4s[g], q4 = q4s[g], sv4 = s4[g];
+            const float uo[4] = {u4.x, u4.y, u4.z, u4.w}, qo[4] = {q4.x, q4.y, q4.z, q4.w};
+            const float sv[4] = {sv4.x, sv4.y, sv4.z, sv4.w};
+            float un[4], qn[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              float w = valid[ib] ? acc[cb][ib][4 * g + e] : 0.f;
+              if (MODE != kFP32) w += uo[e] + qo[e];  // W^t = W^{t-1} + A_k(L^t - L^{t-1}) V
+              float unew, qnew;
+              if constexpr (kFirst) {
+                unew = 0.f;
+                qnew = w;
+              } else {
+                // Z = s.Q_old, U = (U_old + Z - W) ratio, Q = W - U; residual (Z - W)^2
+                const float d = sv[e] * qo[e] - w;
+                unew = (uo[e] + d) * ratio;
+                qnew = w - unew;
+                rsum[ib / 2] += d * d;
+              }
+              un[e] = unew;
+              qn[e] = qnew;
+              qs[4 * g + e] += qnew * qnew;
+              ws[4 * g + e] += w * w;
+            }
+            Up[g] = make_float4(un[0], un[1], un[2], un[3]);
+            Qp[g] = make_float4(qn[0], qn[1], qn[2], qn[3]);
+          }
+          // one piece at a time: keeps the scheduler from hoisting the loads of later
+          // pieces (register pressure)
+          __builtin_amdgcn_sched_barrier(0);
+          if (ib & 1) {  // column partials of one 64-row chunk
+            int vi;
+            const float q = half_sum16(qs, lane, vi);
+            const float w = half_sum16(ws, lane, vi);
+            if ((lane & 1) == 0) {
+              const int col = cc * kColUnit + cb * 32 + acc_col(vi, half);
+              const int rc = ru * kRpu + ib / 2;
+              colq[rc * CG + col] = q;
+              colw[rc * CG + col] = w;
+            }
+#pragma unroll
+            for (int v = 0; v < 16; ++v) qs[v] = ws[v] = 0.f;
+          }
         }
       }
+    };
+    if (MODE == kFP32 && init) {
+      if constexpr (MODE == kFP32) epilogue(std::true_type{});
+    } else {
+      epilogue(std::false_type{});
     }
 #pragma unroll
     for (int r = 0; r < kRpu; ++r) {
@@ -1187,10 +1222,17 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
   float T = 0.f;
   int t0 = 0, t1 = 0, t2 = 0;
   if (in) {
-    t2 = (int)(t % I.m[2]);
-    const int64_t r = t / I.m[2];
-    t1 = (int)(r % I.m[1]);
-    t0 = (int)(r / I.m[1]);
+    if (I.mtot < (int64_t(1) << 31)) {
+      const int t32 = (int)t, r = t32 / I.m[2];
+      t2 = t32 - r * I.m[2];
+      t0 = r / I.m[1];
+      t1 = r - t0 * I.m[1];
+    } else {
+      t2 = (int)(t % I.m[2]);
+      const int64_t r = t / I.m[2];
+      t1 = (int)(r % I.m[1]);
+      t0 = (int)(r / I.m[1]);
+    }
   }
   if (in && phase == kRun) {
     // partials of this iteration's adjoint: the full A_k^*(G V^T), or on a reduced
@@ -1200,20 +1242,58 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
     const int32_t* g2 = I.gtab + I.goff[2] + t2 * I.C[2];
     const int nsg = a.nsg;
     // lane `sub` takes the (c0, c1) pairs congruent to it modulo kLanesPerElem and
-    // sums all c2 and offset groups of each, in a fixed order
+    // sums all c2 and offset groups of each, in a fixed order. The partials come from
+    // other workgroups' writes (not in this XCD's L2), so the loads of a pair are all
+    // issued before any is summed.
     const int C1 = I.C[1], C2 = I.C[2];
     const int npair = I.C[0] * C1;
-    for (int pr = sub; pr < npair; pr += kLanesPerElem) {
-      const int c0 = pr / C1, c1 = pr - c0 * C1;
-      const int e0 = g0[c0], e1 = g1[c1];
-      if ((e0 | e1) < 0) continue;
-      const int tb = ((e0 >> 16) * I.nt[1] + (e1 >> 16)) * I.nt[2];
-      const int pb = ((e0 & 0xffff) * I.E[1] + (e1 & 0xffff)) * I.E[2];
-      for (int c2 = 0; c2 < C2; ++c2) {
-        const int e2 = g2[c2];
-        if (e2 < 0) break;
-        const float* pp = I.part + ((size_t)(tb + (e2 >> 16)) * nsg) * I.E123 + pb + (e2 & 0xffff);
-        for (int g = 0; g < nsg; ++g) T += pp[(size_t)g * I.E123];
+    constexpr int kC2 = 4, kPr = 4;  // fast path: C2 <= 4, <= 4 pairs per lane, one offset group
+    if (C2 <= kC2 && nsg == 1 && npair <= kPr * kLanesPerElem) {
+      int e2v[kC2];
+#pragma unroll
+      for (int c2 = 0; c2 < kC2; ++c2) e2v[c2] = c2 < C2 ? g2[c2] : -1;
+      int e0v[kPr], e1v[kPr];
+#pragma unroll
+      for (int j = 0; j < kPr; ++j) {
+        const int pr = sub + j * kLanesPerElem;
+        e0v[j] = e1v[j] = -1;
+        if (pr < npair) {
+          const int c0 = pr / C1, c1 = pr - c0 * C1;
+          e0v[j] = g0[c0];
+          e1v[j] = g1[c1];
+        }
+      }
+      float v[kPr][kC2];
+#pragma unroll
+      for (int j = 0; j < kPr; ++j) {
+        const int e0 = e0v[j], e1 = e1v[j];
+        const bool okp = (e0 | e1) >= 0;
+        const int tb = ((e0 >> 16) * I.nt[1] + (e1 >> 16)) * I.nt[2];
+        const int pb = ((e0 & 0xffff) * I.E[1] + (e1 & 0xffff)) * I.E[2];
+#pragma unroll
+        for (int c2 = 0; c2 < kC2; ++c2) {
+          const int e2 = e2v[c2];
+          v[j][c2] = 0.f;
+          if (okp && e2 >= 0) v[j][c2] = I.part[(size_t)(tb + (e2 >> 16)) * I.E123 + pb + (e2 & 0xffff)];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kPr; ++j)
+#pragma unroll
+        for (int c2 = 0; c2 < kC2; ++c2) T += v[j][c2];
+    } else {
+      for (int pr = sub; pr < npair; pr += kLanesPerElem) {
+        const int c0 = pr / C1, c1 = pr - c0 * C1;
+        const int e0 = g0[c0], e1 = g1[c1];
+        if ((e0 | e1) < 0) continue;
+        const int tb = ((e0 >> 16) * I.nt[1] + (e1 >> 16)) * I.nt[2];
+        const int pb = ((e0 & 0xffff) * I.E[1] + (e1 & 0xffff)) * I.E[2];
+        for (int c2 = 0; c2 < C2; ++c2) {
+          const int e2 = g2[c2];
+          if (e2 < 0) break;
+          const float* pp = I.part + ((size_t)(tb + (e2 >> 16)) * nsg) * I.E123 + pb + (e2 & 0xffff);
+          for (int g = 0; g < nsg; ++g) T += pp[(size_t)g * I.E123];
+        }
       }
     }
   }

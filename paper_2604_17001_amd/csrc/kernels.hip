@@ -15,6 +15,7 @@
 #include "icnnm_dev.h"
 
 #include <algorithm>
+#include <type_traits>
 
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>

@@ -524,8 +524,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
       }
     };
     // Two compiled forms of the same arithmetic: the first forward of a solve (U = 0,
-    // Q = W, nothing loaded) and every later one. Rows past the tensor's end get
-    // W = 0; their U and Q are zero from the first forward on, so every value
+    // Q = W, nothing loaded) and every later one. FP32: rows past the tensor's end
+    // get W = 0; their U and Q are zero from the first forward on, so every value
     // derived from them is zero as well without further masking.
     auto epilogue = [&](auto init_c) {
       constexpr bool kFirst = decltype(init_c)::value;
@@ -572,18 +572,34 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
             float un[4], qn[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-              float w = valid[ib] ? acc[cb][ib][4 * g + e] : 0.f;
-              if (MODE != kFP32) w += uo[e] + qo[e];  // W^t = W^{t-1} + A_k(L^t - L^{t-1}) V
-              float unew, qnew;
-              if constexpr (kFirst) {
-                unew = 0.f;
-                qnew = w;
+              // Z = s.Q_old, U = (U_old + Z - W) ratio, Q = W - U; residual (Z - W)^2
+              float w, unew, qnew;
+              if constexpr (MODE != kFP32) {
+                // W^t = W^{t-1} + A_k(L^t - L^{t-1}) V; this form (masking after the
+                // update) schedules better in the HBM-bound reduced-precision kernels
+                w = acc[cb][ib][4 * g + e] + (uo[e] + qo[e]);
+                if (!valid[ib]) {
+                  w = 0.f;
+                  unew = 0.f;
+                  qnew = 0.f;
+                } else {
+                  const float z = sv[e] * qo[e];
+                  unew = ((uo[e] + z) - w) * ratio;
+                  qnew = w - unew;
+                  const float d = z - w;
+                  rsum[ib / 2] += d * d;
+                }
               } else {
-                // Z = s.Q_old, U = (U_old + Z - W) ratio, Q = W - U; residual (Z - W)^2
-                const float d = sv[e] * qo[e] - w;
-                unew = (uo[e] + d) * ratio;
-                qnew = w - unew;
-                rsum[ib / 2] += d * d;
+                w = valid[ib] ? acc[cb][ib][4 * g + e] : 0.f;
+                if constexpr (kFirst) {
+                  unew = 0.f;
+                  qnew = w;
+                } else {
+                  const float d = sv[e] * qo[e] - w;
+                  unew = (uo[e] + d) * ratio;
+                  qnew = w - unew;
+                  rsum[ib / 2] += d * d;
+                }
               }
               un[e] = unew;
               qn[e] = qnew;
@@ -593,9 +609,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
             Up[g] = make_float4(un[0], un[1], un[2], un[3]);
             Qp[g] = make_float4(qn[0], qn[1], qn[2], qn[3]);
           }
-          // one piece at a time: keeps the scheduler from hoisting the loads of later
-          // pieces (register pressure)
-          __builtin_amdgcn_sched_barrier(0);
+          // FP32: one piece at a time (keeps the scheduler from hoisting the loads of
+          // later pieces, which costs registers)
+          if constexpr (MODE == kFP32) __builtin_amdgcn_sched_barrier(0);
           if (ib & 1) {  // column partials of one 64-row chunk
             int vi;
             const float q = half_sum16(qs, lane, vi);

@@ -128,6 +128,31 @@ icnnm_status icnnm_learn_eigvecs(icnnm_ctx *ctx, const int64_t kdim[3], int32_t 
                                  const icnnm_shape ref_shapes[], const float *const refs[],
                                  float *V_out, double *eigvals_out, void *stream);
 
+/* Diagnostics of a tensor L0 under a bank of learned convolution eigenvectors
+ * (Definition 2, eq:rkL0, eq:alphaK), for analysis of how well V suits L0:
+ *   sigma_out[i] = || L0 * kappa_i ||_F, the relative convolution eigenvalue of
+ *                  column i of V (the column norms of A_k(L0) V);
+ *   rank_out     = r_K(L0), the number of i with sigma_i > rtol * max_i sigma_i;
+ *   alpha_out    = alpha_K(L0) = || A_k(L0) V D ||_2 with D = diag(1 / sigma_i) on
+ *                  that support and 0 elsewhere (the spectral correlation).
+ * All in FP64: the Gram A_k(L0)^T A_k(L0) from circular autocorrelations on the
+ * device (as in icnnm_learn_eigvecs), C = V^T G V on the device, sigma_i =
+ * sqrt(C_ii), and alpha^2 the largest eigenvalue of D C D on the host. Through
+ * the Gram, a sigma_i far below max sigma is accurate to about 1e-8 max sigma
+ * (sqrt of the FP64 rounding of C_ii); rtol should stay above that.
+ *   shape      host; the tensor and kernel dimensions (as for icnnm_solve)
+ *   L0         device, float32 C-order tensor of the shape
+ *   V          device, k x k float32 row-major [s][i]
+ *   rtol       > 0, relative threshold of the support
+ *   sigma_out  host, k doubles; may be NULL
+ *   rank_out   host; may be NULL
+ *   alpha_out  host; may be NULL
+ * Blocks until the outputs are written. Errors: ICNNM_E_INVALID (bad shape, NULL
+ * L0 or V, rtol <= 0), ICNNM_E_NOMEM, ICNNM_E_BUDGET, ICNNM_E_DEVICE. */
+icnnm_status icnnm_diagnostics(icnnm_ctx *ctx, const icnnm_shape *shape, const float *L0, const float *V,
+                               double rtol, double *sigma_out, int32_t *rank_out, double *alpha_out,
+                               void *stream);
+
 /* Solve one completion instance (Section III-D iteration).
  *   shape   host; M, mask, L_out device arrays of prod(m) entries
  *   V       device, k*k float32 orthogonal eigenvector bank

@@ -106,6 +106,10 @@ void launch_check_v(const float* V, int k, float* out_maxdev, hipStream_t st);
 void launch_autocorr(const float* L, const int32_t* m, const int32_t* k, double* R,
                      hipStream_t st);
 void launch_gram_expand(const double* R, const int32_t* k, double* G, hipStream_t st);
+// FP64 products for the diagnostics: C = op(A) B for n x n row-major matrices
+// (op(A) = A^T when trans_a), and a float -> double copy of n values
+void launch_gemm_f64(const double* A, int trans_a, const double* B, double* C, int n, hipStream_t st);
+void launch_f32_to_f64(const float* src, double* dst, int64_t n, hipStream_t st);
 void launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t st);
 
 }  // namespace icnnm

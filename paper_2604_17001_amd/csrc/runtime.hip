@@ -914,6 +914,66 @@ static icnnm_status do_learn(icnnm_ctx* c, const int64_t kdim_in[3], int b, cons
   return ICNNM_OK;
 }
 
+// Diagnostics of L0 under V (Definition 2, eq:rkL0, eq:alphaK): the Gram of A_k(L0)
+// from circular autocorrelations (as in learning), C = V^T G V on the device in FP64,
+// sigma_i = sqrt(C_ii), r_K = #{sigma_i > rtol max sigma}, alpha_K^2 = the largest
+// eigenvalue of D C D with D = diag(1 / sigma_i) on the support.
+static icnnm_status do_diag(icnnm_ctx* c, const icnnm_shape* shape, const float* L0, const float* V, double rtol,
+                            double* sigma_out, int32_t* rank_out, double* alpha_out, void* user_stream) {
+  if (!L0 || !V) throw Error(ICNNM_E_INVALID, "L0 and V must be device pointers");
+  if (!(rtol > 0.0)) throw Error(ICNNM_E_INVALID, "rtol must be positive");
+  int m[3], kd[3];
+  normalize_shape(shape, m, kd);
+  const int k = kd[0] * kd[1] * kd[2];
+  std::lock_guard<std::recursive_mutex> lock(c->mu);
+  hipStream_t st = enter(c, user_stream);
+  const int ndiff = (2 * kd[0] - 1) * (2 * kd[1] - 1) * (2 * kd[2] - 1);
+  const size_t kk = (size_t)k * k;
+  DevBuf R, G, Vd, T, Cm;
+  R.ensure(&c->budget, (size_t)ndiff * 8);
+  G.ensure(&c->budget, kk * 8);
+  Vd.ensure(&c->budget, kk * 8);
+  T.ensure(&c->budget, kk * 8);
+  Cm.ensure(&c->budget, kk * 8);
+  HIPCK(hipMemsetAsync(R.p, 0, (size_t)ndiff * 8, st));
+  launch_autocorr(L0, m, kd, R.as<double>(), st);
+  launch_gram_expand(R.as<double>(), kd, G.as<double>(), st);
+  launch_f32_to_f64(V, Vd.as<double>(), (int64_t)kk, st);
+  launch_gemm_f64(G.as<double>(), 0, Vd.as<double>(), T.as<double>(), k, st);   // T = G V
+  launch_gemm_f64(Vd.as<double>(), 1, T.as<double>(), Cm.as<double>(), k, st);  // C = V^T T
+  HIPCK(hipGetLastError());
+  std::vector<double> Ch(kk);
+  HIPCK(hipMemcpyAsync(Ch.data(), Cm.p, kk * 8, hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  leave(c, user_stream);
+  std::vector<double> sig(k);
+  double smax = 0.0;
+  for (int i = 0; i < k; ++i) {
+    sig[i] = std::sqrt(std::max(Ch[(size_t)i * k + i], 0.0));
+    smax = std::max(smax, sig[i]);
+  }
+  const double thr = rtol * std::max(smax, 1e-300);
+  std::vector<double> d(k, 0.0);
+  int rank = 0;
+  for (int i = 0; i < k; ++i)
+    if (sig[i] > thr) {
+      d[i] = 1.0 / sig[i];
+      ++rank;
+    }
+  double alpha = 0.0;
+  if (alpha_out) {
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) Ch[(size_t)i * k + j] *= d[i] * d[j];
+    std::vector<double> w, Vv;
+    sym_eig(Ch, k, w, Vv);
+    alpha = std::sqrt(std::max(w.empty() ? 0.0 : w[0], 0.0));
+  }
+  if (sigma_out) std::copy(sig.begin(), sig.end(), sigma_out);
+  if (rank_out) *rank_out = rank;
+  if (alpha_out) *alpha_out = alpha;
+  return ICNNM_OK;
+}
+
 }  // namespace icnnm
 
 // ================================================================================ C ABI
@@ -972,6 +1032,12 @@ icnnm_status icnnm_learn_eigvecs(icnnm_ctx* c, const int64_t kdim[3], int32_t b,
                                  const float* const refs[], float* V_out, double* eigvals_out, void* stream) {
   if (!c) return ICNNM_E_INVALID;
   return guarded(c, [&] { return do_learn(c, kdim, b, ref_shapes, refs, V_out, eigvals_out, stream); });
+}
+
+icnnm_status icnnm_diagnostics(icnnm_ctx* c, const icnnm_shape* shape, const float* L0, const float* V, double rtol,
+                               double* sigma_out, int32_t* rank_out, double* alpha_out, void* stream) {
+  if (!c) return ICNNM_E_INVALID;
+  return guarded(c, [&] { return do_diag(c, shape, L0, V, rtol, sigma_out, rank_out, alpha_out, stream); });
 }
 
 icnnm_status icnnm_solve(icnnm_ctx* c, const icnnm_shape* shape, const float* M, const uint8_t* mask,

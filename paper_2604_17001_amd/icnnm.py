@@ -23,7 +23,8 @@ E_INVALID, E_NOMEM, E_BUDGET, E_DEVICE, E_NUMERIC, E_NOTFOUND = -1, -2, -3, -4, 
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
 
 EXPORTS = ["icnnm_params_default", "icnnm_create", "icnnm_destroy", "icnnm_last_error",
-           "icnnm_learn_eigvecs", "icnnm_solve", "icnnm_solve_batch", "icnnm_submit", "icnnm_poll",
+           "icnnm_learn_eigvecs", "icnnm_diagnostics", "icnnm_solve", "icnnm_solve_batch", "icnnm_submit",
+           "icnnm_poll",
            "icnnm_set_profiling", "icnnm_stage_times"]
 STAGES = ("colnorm", "adjoint", "lstep", "forward")
 
@@ -70,6 +71,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.icnnm_learn_eigvecs.argtypes = [P, C.POINTER(C.c_int64), C.c_int32, C.POINTER(Shape),
                                         C.POINTER(P), P, C.POINTER(C.c_double), P]
     lib.icnnm_learn_eigvecs.restype = C.c_int32
+    lib.icnnm_diagnostics.argtypes = [P, C.POINTER(Shape), P, P, C.c_double, C.POINTER(C.c_double),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_double), P]
+    lib.icnnm_diagnostics.restype = C.c_int32
     lib.icnnm_solve.argtypes = [P, C.POINTER(Shape), P, P, P, C.POINTER(Params), P, C.POINTER(Info), P]
     lib.icnnm_solve.restype = C.c_int32
     lib.icnnm_solve_batch.argtypes = [P, C.c_int32, C.POINTER(Shape), C.POINTER(P), C.POINTER(P), P,
@@ -184,6 +188,24 @@ class Library:
         if rc != OK:
             self._raise(rc)
         return V, w
+
+    def diagnostics(self, L0, V, kdims, rtol=1e-10):
+        """Relative convolution eigenvalues, relative rank and spectral correlation of
+        L0 under V (Definition 2, eq:rkL0, eq:alphaK). Returns (sigma, r_K, alpha_K)."""
+        import torch
+        _check_tensor(L0, torch.float32, name="L0")
+        k = int(np.prod(kdims))
+        _check_tensor(V, torch.float32, (k, k), name="V")
+        shape = make_shape(L0.shape, kdims)
+        sigma = np.zeros(k, dtype=np.float64)
+        rank = C.c_int32(0)
+        alpha = C.c_double(0.0)
+        rc = self.lib.icnnm_diagnostics(self.ctx, C.byref(shape), _ptr(L0), _ptr(V), float(rtol),
+                                        sigma.ctypes.data_as(C.POINTER(C.c_double)), C.byref(rank),
+                                        C.byref(alpha), _stream())
+        if rc != OK:
+            self._raise(rc)
+        return sigma, int(rank.value), float(alpha.value)
 
     def solve(self, M, mask, V, kdims, out=None, **kw):
         """Complete one tensor. Returns (L, info dict)."""

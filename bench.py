@@ -52,11 +52,22 @@ def _workload(name):
             "128x128x32": inputs.interpolation_128x128x32, "batch": inputs.batch_uneven}[name]()
 
 
+def _count_tiles(infos):
+    out = {}
+    for i in infos:
+        key = "x".join(str(x) for x in i["tile"])
+        out[key] = out.get(key, 0) + 1
+    return out
+
+
 def _batch_main(args):
     """Batching form: 64 uneven instances (extents {32..128}^2 x {8,16,32}, 8x8x4 kernel,
     one shared V) solved in joint launches; a step is one solve of the whole batch."""
     import torch
     from paper_2604_17001_amd import icnnm
+    if not args.no_autotune:
+        # tile boxes measured per instance shape during the untimed warm-up
+        os.environ["ICNNM_AUTOTUNE"] = "1"
     wl = _workload("batch")
     iters = args.iters or wl.iters
     lib = icnnm.Library.get()
@@ -79,7 +90,11 @@ def _batch_main(args):
     dt = time.perf_counter() - t0
     n = len(wl.problems)
     msum = sum(p.m for p in wl.problems)
-    # one-at-a-time FP32 solves of the same instances, the baseline form
+    # one-at-a-time FP32 solves of the same instances, the baseline form (one untimed
+    # pass first: per-shape set-up and, with autotuning, tile measurement)
+    for M, mk, o in zip(Ms, masks, outs):
+        lib.solve(M, mk, V, wl.kdims, out=o, max_iter=iters)
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
     for M, mk, o in zip(Ms, masks, outs):
         lib.solve(M, mk, V, wl.kdims, out=o, max_iter=iters)
@@ -92,7 +107,8 @@ def _batch_main(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else args.precision,
            "data": "synthetic",
            "config": {"workload": wl.name, "instances": n, "sum_m": msum, "kdims": list(wl.kdims),
-                      "iters": iters, "precision": args.precision},
+                      "iters": iters, "precision": args.precision, "autotune": not args.no_autotune},
+           "tiles": {k: v for k, v in sorted(_count_tiles(infos).items())},
            "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
            "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
            "tflops_effective": round(flops * args.steps / dt / 1e12, 2),
@@ -182,6 +198,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-4, help="serve: retirement residual")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: HBM budget of the server")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--no-autotune", action="store_true", help="batch: cost-model tile boxes only")
     ap.add_argument("--cpu-sample-iters", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")

@@ -29,6 +29,11 @@
  *  - Errors: every call returns an icnnm_status; on error, nothing is written
  *    to outputs beyond what is documented and icnnm_last_error() describes the
  *    failure. No C++ exception crosses this boundary.
+ *  - Tile boxes: chosen by a cost model, or with the environment variable
+ *    ICNNM_AUTOTUNE=1 by timing the best few candidates on the instance (solve
+ *    and solve_batch; cached per shape in the context and, if
+ *    ICNNM_AUTOTUNE_CACHE names a file, across processes). icnnm_info.tile
+ *    reports the box used.
  *  - Thread safety: a context may be used from several host threads; calls
  *    on one context are serialised internally. icnnm_submit/icnnm_poll may be
  *    called concurrently with each other.
@@ -96,6 +101,8 @@ typedef struct {
   double theta_final;
   double t_queue_s;  /* submit only: time from submit to first device work */
   double t_device_s; /* wall time from first device work to completion */
+  int32_t tile[3];   /* tile box b_1..b_3 the solve ran with (order-3 form; from the
+                        cost-model planner, or measured with ICNNM_AUTOTUNE=1) */
 } icnnm_info;
 
 /* Default parameters: lambda = +inf, theta0 auto, rho 1.1, theta_max 1e10,

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -134,9 +135,10 @@ static int lds_adjoint_floats(const Plan& p, int kp) {
   return (SGW / rounds) * (p.bm + 4);
 }
 
-static Plan make_plan(const int m[3], const int k[3], int kp) {
-  Plan best{};
-  double best_cost = 1e300;
+// Every admissible tile box with its cost-model estimate, cheapest first (the plans
+// are not yet finished: see finish_plan).
+static std::vector<std::pair<double, Plan>> plan_candidates(const int m[3], const int k[3], int kp) {
+  std::vector<std::pair<double, Plan>> out;
   const int nsg = (kp + kGroup - 1) / kGroup;
   // ICNNM_TILE=b0,b1,b2 forces one tile box (used to compare tile shapes)
   int force[3] = {0, 0, 0};
@@ -193,15 +195,19 @@ static Plan make_plan(const int m[3], const int k[3], int kp) {
         // 128-row tiles admit the operand-reusing tiled adjoint when kp is a multiple of 256
         const double tiled = (kp % kGroup == 0 && bm != 128) ? 1.3 : 1.0;
         const double cost = rounds * (std::max(upw, 1.0) + 0.5) / eff * padded * (1.0 + halo) * inner * gather * tiled;
-        if (cost < best_cost - 1e-12) {
-          best_cost = cost;
-          best = p;
-        }
+        out.emplace_back(cost, p);
       }
     }
   }
-  if (best_cost >= 1e300) throw Error(ICNNM_E_INVALID, "no tile shape fits this problem");
-  Plan& p = best;
+  std::stable_sort(out.begin(), out.end(),
+                   [](const std::pair<double, Plan>& a, const std::pair<double, Plan>& b) { return a.first < b.first; });
+  return out;
+}
+
+// sizes and gather tables of a chosen tile box
+static void finish_plan(Plan& p, int kp) {
+  const int* m = p.m;
+  const int* k = p.k;
   p.mtot = (int64_t)m[0] * m[1] * m[2];
   p.nlblk = (int)((p.mtot + kLStepElems - 1) / kLStepElems);
   p.nslice = kp / 4;  // column-norm blocks: four columns (one wavefront each) per block
@@ -226,7 +232,26 @@ static Plan make_plan(const int m[3], const int k[3], int kp) {
     }
     off += m[d] * C;
   }
-  return best;
+}
+
+// the cost model's choice
+static Plan make_plan(const int m[3], const int k[3], int kp) {
+  auto c = plan_candidates(m, k, kp);
+  if (c.empty()) throw Error(ICNNM_E_INVALID, "no tile shape fits this problem");
+  Plan p = c.front().second;
+  finish_plan(p, kp);
+  return p;
+}
+
+// the admissible plan with tile box b, or the cost model's choice if b is not admissible
+static Plan plan_with_box(const int m[3], const int k[3], int kp, const int b[3]) {
+  for (auto& cp : plan_candidates(m, k, kp))
+    if (cp.second.b[0] == b[0] && cp.second.b[1] == b[1] && cp.second.b[2] == b[2]) {
+      Plan p = cp.second;
+      finish_plan(p, kp);
+      return p;
+    }
+  return make_plan(m, k, kp);
 }
 
 // ------------------------------------------------------------------------------ group executor
@@ -610,6 +635,9 @@ struct icnnm_ctx {
   bool stop = false;
   std::thread server;
   icnnm::Group::Prof prof;  // stage timing of synchronous calls
+  // autotuned tile boxes by (shape, kernel, precision); loaded once from the cache file
+  std::map<std::string, std::array<int, 3>> tuned;
+  bool tuned_loaded = false;
 };
 
 namespace icnnm {
@@ -711,6 +739,133 @@ static std::string key_of(const int m[3], const int kd[3], const icnnm_params* p
   return buf;
 }
 
+// ------------------------------------------------------------------------------ autotuner
+// With ICNNM_AUTOTUNE=1 the tile box of an instance is chosen by measurement: the
+// cost model's kTuneCandidates cheapest boxes each run kTuneRounds solver rounds of
+// the actual instance (scratch state and output, after two warm-up iterations) and
+// the fastest is kept, per (shape, kernel, precision), for the life of the context
+// and, if ICNNM_AUTOTUNE_CACHE names a file, across processes (one line per key:
+// "icnnm-tile m0 m1 m2 k0 k1 k2 precision class b0 b1 b2"). Without it the cost
+// model decides alone. In a batch the members share kernel variants (the tiled
+// adjoint needs 128-row tiles, the line gather line-friendly boxes), so there the
+// search keeps to boxes of the cost model's class (same rows per tile, same gather),
+// recorded as class 1 in the key. Tile boxes change the summation order of the
+// col2im and of the column-norm partials, not the method: results agree to rounding.
+constexpr int kTuneCandidates = 4;
+constexpr int kTuneRounds = 10;
+
+static bool autotune_on() {
+  const char* e = getenv("ICNNM_AUTOTUNE");
+  return e && atoi(e) != 0;
+}
+
+static std::string tune_key(const int m[3], const int kd[3], int prec, int cls) {
+  char buf[128];
+  snprintf(buf, sizeof buf, "%d %d %d %d %d %d %d %d", m[0], m[1], m[2], kd[0], kd[1], kd[2], prec, cls);
+  return buf;
+}
+
+static void load_tune_cache(icnnm_ctx* c) {
+  if (c->tuned_loaded) return;
+  c->tuned_loaded = true;
+  const char* path = getenv("ICNNM_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char line[256];
+  while (fgets(line, sizeof line, f)) {
+    int v[11];
+    if (sscanf(line, "icnnm-tile %d %d %d %d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5],
+               &v[6], &v[7], &v[8], &v[9], &v[10]) == 11)
+      c->tuned[tune_key(v, v + 3, v[6], v[7])] = {v[8], v[9], v[10]};
+  }
+  fclose(f);
+}
+
+static void save_tune_entry(const std::string& key, const int b[3]) {
+  const char* path = getenv("ICNNM_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "icnnm-tile %s %d %d %d\n", key.c_str(), b[0], b[1], b[2]);
+  fclose(f);
+}
+
+// seconds per solver round of one instance under plan p
+static double time_plan(icnnm_ctx* c, const Plan& p, const int kd[3], int prec, const float* M,
+                        const uint8_t* mask, const float* V, hipStream_t st) {
+  DevBuf Ls;
+  Ls.ensure(&c->budget, (size_t)p.mtot * 4);
+  Group g(&c->budget, kd, prec, 1);
+  Member mb;
+  mb.plan = p;
+  icnnm_params_default(&mb.params);
+  mb.params.precision = prec;
+  mb.params.max_iter = 1 << 20;
+  mb.M = M;
+  mb.mask = mask;
+  mb.Lout = Ls.as<float>();
+  g.attach(&mb, st);
+  g.set_v(V, st);
+  g.run(4, st, false, 1);  // new -> init -> two iterations
+  hipEvent_t e0, e1;
+  HIPCK(hipEventCreate(&e0));
+  HIPCK(hipEventCreate(&e1));
+  HIPCK(hipEventRecord(e0, st));
+  g.run(kTuneRounds, st, false, 1);
+  HIPCK(hipEventRecord(e1, st));
+  HIPCK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  g.detach(&mb);
+  return 1e-3 * ms / kTuneRounds;
+}
+
+// tile plan of an instance: measured (autotuner) or the cost model's
+static Plan choose_plan(icnnm_ctx* c, const int m[3], const int kd[3], int kp, int prec, const float* M,
+                        const uint8_t* mask, const float* V, hipStream_t st, bool same_class,
+                        bool may_measure = true) {
+  if (!autotune_on() || getenv("ICNNM_TILE")) return make_plan(m, kd, kp);
+  load_tune_cache(c);
+  const std::string key = tune_key(m, kd, prec, same_class ? 1 : 0);
+  auto it = c->tuned.find(key);
+  if (it != c->tuned.end()) return plan_with_box(m, kd, kp, it->second.data());
+  if (!may_measure) return make_plan(m, kd, kp);
+  auto all = plan_candidates(m, kd, kp);
+  if (all.empty()) throw Error(ICNNM_E_INVALID, "no tile shape fits this problem");
+  std::vector<Plan> cands;
+  const Plan& first = all.front().second;
+  for (auto& cp : all) {
+    if ((int)cands.size() == kTuneCandidates) break;
+    if (same_class && (cp.second.bm != first.bm || lines_gather_fits(cp.second) != lines_gather_fits(first)))
+      continue;
+    cands.push_back(cp.second);
+  }
+  int best = 0;
+  double best_t = 1e300;
+  for (int i = 0; i < (int)cands.size(); ++i) {
+    Plan p = cands[i];
+    finish_plan(p, kp);
+    const double t = time_plan(c, p, kd, prec, M, mask, V, st);
+    if (t < best_t) {
+      best_t = t;
+      best = i;
+    }
+  }
+  Plan p = cands[best];
+  finish_plan(p, kp);
+  c->tuned[key] = {p.b[0], p.b[1], p.b[2]};
+  save_tune_entry(key, p.b);
+  return p;
+}
+
+static void fill_tile(const Plan& p, icnnm_info* info) {
+  if (!info) return;
+  for (int d = 0; d < 3; ++d) info->tile[d] = p.b[d];
+}
+
 static icnnm_status do_solve(icnnm_ctx* c, const icnnm_shape* shape, const float* M, const uint8_t* mask,
                              const float* V, const icnnm_params* params, float* L_out, icnnm_info* info,
                              void* user_stream) {
@@ -730,7 +885,7 @@ static icnnm_status do_solve(icnnm_ctx* c, const icnnm_shape* shape, const float
   if (it == c->cache.end()) {
     auto grp = std::make_unique<Group>(&c->budget, kd, params->precision, 1);
     auto mem = std::make_unique<Member>();
-    mem->plan = make_plan(m, kd, grp->kp);
+    mem->plan = choose_plan(c, m, kd, grp->kp, params->precision, M, mask, V, st, false);
     mem->params = *params;
     mem->M = M;
     mem->mask = mask;
@@ -789,6 +944,7 @@ static icnnm_status do_solve(icnnm_ctx* c, const icnnm_shape* shape, const float
   const InstState& s = sts[mb->slot];
   if (info) {
     fill_info(s, info);
+    fill_tile(mb->plan, info);
     info->t_queue_s = 0;
     info->t_device_s = now_s() - t0;
   }
@@ -831,7 +987,7 @@ static icnnm_status do_solve_batch(icnnm_ctx* c, int count, const icnnm_shape* s
   for (int i = 0; i < count; ++i) {
     int m[3], kd[3];
     normalize_shape(&shapes[i], m, kd);
-    mems[i]->plan = make_plan(m, kd, g.kp);
+    mems[i]->plan = choose_plan(c, m, kd, g.kp, params->precision, Ms[i], masks[i], V, st, true);
     g.attach(mems[i].get(), st);
   }
   g.set_v(V, st);
@@ -861,6 +1017,7 @@ static icnnm_status do_solve_batch(icnnm_ctx* c, int count, const icnnm_shape* s
     const InstState& s = sts[mems[i]->slot];
     if (infos) {
       fill_info(s, &infos[i]);
+      fill_tile(mems[i]->plan, &infos[i]);
       infos[i].t_queue_s = 0;
       infos[i].t_device_s = now_s() - t0;
     }
@@ -1177,6 +1334,7 @@ static void serve_loop(icnnm_ctx* c) {
         Done d{};
         d.status = rc != ICNNM_OK ? rc : (s->status != 0 ? ICNNM_E_NUMERIC : ICNNM_OK);
         if (s) fill_info(*s, &d.info);
+        fill_tile(mb->plan, &d.info);
         const double t = now_s();
         d.info.t_queue_s = mb->t_start - mb->t_submit;
         d.info.t_device_s = t - mb->t_start;

@@ -42,10 +42,12 @@ class Params(C.Structure):
 class Info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("r_primal", C.c_double),
                 ("r_change", C.c_double), ("objective", C.c_double), ("theta_final", C.c_double),
-                ("t_queue_s", C.c_double), ("t_device_s", C.c_double)]
+                ("t_queue_s", C.c_double), ("t_device_s", C.c_double), ("tile", C.c_int32 * 3)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["tile"] = tuple(self.tile)
+        return d
 
 
 class IcnnmError(RuntimeError):

@@ -40,10 +40,28 @@ def test_params_default():
     assert p.max_iter == 100 and p.tol == 0 and p.precision == 0 and p.refresh_every == 10 and p.check_v == 0
 
 
-def test_struct_layouts_match_header():
-    assert C.sizeof(icnnm.Shape) == 56
-    assert C.sizeof(icnnm.Params) == 64
-    assert C.sizeof(icnnm.Info) == 56
+def test_struct_layouts_match_header(tmp_path):
+    # sizes and field offsets as the C compiler lays out include/icnnm.h
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    src.write_text("""#include <stdio.h>
+#include <stddef.h>
+#include "icnnm.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(icnnm_shape), sizeof(icnnm_params), sizeof(icnnm_info),
+         offsetof(icnnm_info, t_device_s), offsetof(icnnm_info, tile), offsetof(icnnm_params, check_v));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == [C.sizeof(icnnm.Shape), C.sizeof(icnnm.Params), C.sizeof(icnnm.Info),
+                   icnnm.Info.t_device_s.offset, icnnm.Info.tile.offset, icnnm.Params.check_v.offset]
 
 
 def test_null_context_is_rejected():

@@ -805,20 +805,24 @@ static double time_plan(icnnm_ctx* c, const Plan& p, const int kd[3], int prec, 
   mb.M = M;
   mb.mask = mask;
   mb.Lout = Ls.as<float>();
+  struct Events {  // destroyed on every exit path
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Events() {
+      for (hipEvent_t x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev;
+  HIPCK(hipEventCreate(&ev.e[0]));
+  HIPCK(hipEventCreate(&ev.e[1]));
   g.attach(&mb, st);
   g.set_v(V, st);
   g.run(4, st, false, 1);  // new -> init -> two iterations
-  hipEvent_t e0, e1;
-  HIPCK(hipEventCreate(&e0));
-  HIPCK(hipEventCreate(&e1));
-  HIPCK(hipEventRecord(e0, st));
+  HIPCK(hipEventRecord(ev.e[0], st));
   g.run(kTuneRounds, st, false, 1);
-  HIPCK(hipEventRecord(e1, st));
-  HIPCK(hipEventSynchronize(e1));
+  HIPCK(hipEventRecord(ev.e[1], st));
+  HIPCK(hipEventSynchronize(ev.e[1]));
   float ms = 0.f;
-  HIPCK(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  HIPCK(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
   g.detach(&mb);
   return 1e-3 * ms / kTuneRounds;
 }
@@ -848,12 +852,21 @@ static Plan choose_plan(icnnm_ctx* c, const int m[3], const int kd[3], int kp, i
   for (int i = 0; i < (int)cands.size(); ++i) {
     Plan p = cands[i];
     finish_plan(p, kp);
-    const double t = time_plan(c, p, kd, prec, M, mask, V, st);
+    double t = 1e300;
+    try {
+      t = time_plan(c, p, kd, prec, M, mask, V, st);
+    } catch (const Error& e) {
+      // a candidate whose state does not fit the budget is skipped; any other error
+      // is the solve's own
+      if (e.code != ICNNM_E_BUDGET && e.code != ICNNM_E_NOMEM) throw;
+      HIPCK(hipStreamSynchronize(st));
+    }
     if (t < best_t) {
       best_t = t;
       best = i;
     }
   }
+  if (best_t >= 1e300) return make_plan(m, kd, kp);  // nothing could be timed
   Plan p = cands[best];
   finish_plan(p, kp);
   c->tuned[key] = {p.b[0], p.b[1], p.b[2]};

@@ -41,11 +41,11 @@ struct alignas(16) InstState {
   int32_t iters;
   int32_t converged;
   int32_t status;     // 0 ok, -5 numeric
-  uint32_t counter;   // arrival counter of the column-norm reduction (reset by the last block)
   int32_t refresh;    // reduced precision: this iteration evaluates both contractions in FP32
-  int32_t pad[2];
+  int32_t pad[3];
   double ratio_prev;  // ratio of the previous iteration (reconstructs the previous G)
 };
+static_assert(sizeof(InstState) == 96, "InstState is copied between host and device as is");
 
 struct alignas(16) InstDev {
   int32_t m[3], k[3], b[3], E[3], nt[3], C[3], goff[3];

@@ -243,6 +243,28 @@ static Plan make_plan(const int m[3], const int k[3], int kp) {
   return p;
 }
 
+// A member of a joint launch (batch or server group): the kernel variants are chosen
+// per launch, so one member with tiles unfit for the tiled adjoint (128 rows) or the
+// line gather moves every member to the slower variant; and the launch has the
+// workgroups of all members, so a small member gains nothing from smaller tiles.
+// Hence the cheapest box that keeps both, when there is one.
+static bool keeps_shared_variants(const Plan& p, int kp) {
+  return (kp % kGroup != 0 || p.bm == 128) && (p.k[2] != 4 || lines_gather_fits(p));
+}
+
+static Plan make_plan_shared(const int m[3], const int k[3], int kp) {
+  auto c = plan_candidates(m, k, kp);
+  if (c.empty()) throw Error(ICNNM_E_INVALID, "no tile shape fits this problem");
+  Plan p = c.front().second;
+  for (auto& cp : c)
+    if (keeps_shared_variants(cp.second, kp)) {
+      p = cp.second;
+      break;
+    }
+  finish_plan(p, kp);
+  return p;
+}
+
 // the admissible plan with tile box b, or the cost model's choice if b is not admissible
 static Plan plan_with_box(const int m[3], const int k[3], int kp, const int b[3]) {
   for (auto& cp : plan_candidates(m, k, kp))
@@ -831,16 +853,17 @@ static double time_plan(icnnm_ctx* c, const Plan& p, const int kd[3], int prec, 
 static Plan choose_plan(icnnm_ctx* c, const int m[3], const int kd[3], int kp, int prec, const float* M,
                         const uint8_t* mask, const float* V, hipStream_t st, bool same_class,
                         bool may_measure = true) {
-  if (!autotune_on() || getenv("ICNNM_TILE")) return make_plan(m, kd, kp);
+  auto base_plan = [&] { return same_class ? make_plan_shared(m, kd, kp) : make_plan(m, kd, kp); };
+  if (!autotune_on() || getenv("ICNNM_TILE")) return base_plan();
   load_tune_cache(c);
   const std::string key = tune_key(m, kd, prec, same_class ? 1 : 0);
   auto it = c->tuned.find(key);
   if (it != c->tuned.end()) return plan_with_box(m, kd, kp, it->second.data());
-  if (!may_measure) return make_plan(m, kd, kp);
+  if (!may_measure) return base_plan();
   auto all = plan_candidates(m, kd, kp);
   if (all.empty()) throw Error(ICNNM_E_INVALID, "no tile shape fits this problem");
   std::vector<Plan> cands;
-  const Plan& first = all.front().second;
+  const Plan first = base_plan();
   for (auto& cp : all) {
     if ((int)cands.size() == kTuneCandidates) break;
     if (same_class && (cp.second.bm != first.bm || lines_gather_fits(cp.second) != lines_gather_fits(first)))
@@ -866,7 +889,7 @@ static Plan choose_plan(icnnm_ctx* c, const int m[3], const int kd[3], int kp, i
       best = i;
     }
   }
-  if (best_t >= 1e300) return make_plan(m, kd, kp);  // nothing could be timed
+  if (best_t >= 1e300) return base_plan();  // nothing could be timed
   Plan p = cands[best];
   finish_plan(p, kp);
   c->tuned[key] = {p.b[0], p.b[1], p.b[2]};
@@ -1288,7 +1311,7 @@ static void serve_loop(icnnm_ctx* c) {
           sg.g->set_v(r.V, sg.stream);
         }
         auto mb = std::make_unique<Member>();
-        mb->plan = make_plan(r.m, r.kd, sg.g->kp);
+        mb->plan = make_plan_shared(r.m, r.kd, sg.g->kp);
         mb->params = r.params;
         mb->M = r.M;
         mb->mask = r.mask;
@@ -1380,7 +1403,7 @@ static icnnm_status do_submit(icnnm_ctx* c, const icnnm_shape* shape, const floa
   const int k = r.kd[0] * r.kd[1] * r.kd[2];
   const int kp = padded_k(k);
   const int nsg = (kp + kGroup - 1) / kGroup;
-  const Plan p = make_plan(r.m, r.kd, kp);
+  const Plan p = make_plan_shared(r.m, r.kd, kp);  // as the server will plan it
   r.bytes = member_bytes(p, kp, nsg, nsg, params->precision);
   // V operand copies: three FP32 layouts, three more in BF16/FP16 for the reduced precisions
   const size_t vbytes = (size_t)kp * kp * (12 + (params->precision != 0 ? 6 : 0));

@@ -36,19 +36,27 @@ def test_repeated_solve_is_bitwise_identical(lib, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_batch_member_equals_alone_bitwise(lib, prec):
-    # uneven sizes that all plan 128-row tiles with 8-row innermost extents, so the
-    # joint launch uses the same kernel variants as the solo solves
+def test_batch_member_equals_alone_bitwise(lib, prec, monkeypatch):
+    # uneven sizes; members of a joint launch plan tiles that keep the launch's fast
+    # kernel variants, so each solo solve is forced to its member's tile box (fresh
+    # context: no cached plan of the shape) and must then agree bit for bit
+    from paper_2604_17001_amd import icnnm
     kd = (8, 8, 4)
     dims_list = [(32, 32, 16), (48, 32, 8), (64, 32, 16)]
     V, _ = O.learn(inputs.random_refs((32, 32, 16), 3, 40), kd)
     V32 = V.astype(np.float32)
     probs = [inputs.random_problem(d, kd, 0.4, 41 + i) for i, d in enumerate(dims_list)]
     print(f"[gpu] batch vs alone {prec}", flush=True)
-    Ls, _ = lib.solve_batch([_dev(p.M) for p in probs], [_dev(p.mask) for p in probs], _dev(V32), kd,
-                            max_iter=30, precision=prec)
-    for p, Lb in zip(probs, Ls):
-        La, _ = lib.solve(_dev(p.M), _dev(p.mask), _dev(V32), kd, max_iter=30, precision=prec)
+    Ls, infos = lib.solve_batch([_dev(p.M) for p in probs], [_dev(p.mask) for p in probs], _dev(V32), kd,
+                                max_iter=30, precision=prec)
+    for p, Lb, info in zip(probs, Ls, infos):
+        monkeypatch.setenv("ICNNM_TILE", ",".join(str(x) for x in info["tile"]))
+        solo = icnnm.Library()
+        try:
+            La, ia = solo.solve(_dev(p.M), _dev(p.mask), _dev(V32), kd, max_iter=30, precision=prec)
+        finally:
+            solo.close()
+        assert ia["tile"] == info["tile"]
         assert np.array_equal(Lb.cpu().numpy(), La.cpu().numpy())
 
 

@@ -331,6 +331,8 @@ struct Group {
   bool dirty = true;
   hipGraphExec_t gexec = nullptr;
   int graph_rounds = 0;
+  // graphs of run_aligned: (precision of the rounds, number of rounds) -> graph
+  std::map<std::pair<int, int>, hipGraphExec_t> kgraphs;
   // stage timing (events around each launch) when profiling is on
   struct Prof {
     bool on = false;
@@ -354,6 +356,8 @@ struct Group {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     gexec = nullptr;
     graph_rounds = 0;
+    for (auto& kv : kgraphs) (void)hipGraphExecDestroy(kv.second);
+    kgraphs.clear();
   }
 
   void set_v(const float* V, hipStream_t st) {
@@ -516,23 +520,27 @@ struct Group {
 
   // FP32 adjoint (initialisation, FP32 solves, refresh iterations) and, for the reduced
   // precisions, the delta adjoint; each returns at once for instances it does not serve
-  void launch_adjoints(const StageArgs& a, hipStream_t st) const {
+  // only < 0: both precisions' kernels (each returns at once for the iterations of the
+  // other); otherwise only the kernels of precision `only`
+  void launch_adjoints(const StageArgs& a, hipStream_t st, int only = -1) const {
+    const bool f32 = only < 0 || only == kFP32, lo = prec != kFP32 && (only < 0 || only == prec);
     if (big) {
-      launch_adjoint_big(a, ntiles_total, kFP32, gv, st);
-      if (prec != kFP32) launch_adjoint_big(a, ntiles_total, prec, gv, st);
+      if (f32) launch_adjoint_big(a, ntiles_total, kFP32, gv, st);
+      if (lo) launch_adjoint_big(a, ntiles_total, prec, gv, st);
     } else {
-      launch_adjoint(a, ntiles_total, lds_adj, kFP32, gv, st);
-      if (prec != kFP32) launch_adjoint(a, ntiles_total, lds_adj, prec, gv, st);
+      if (f32) launch_adjoint(a, ntiles_total, lds_adj, kFP32, gv, st);
+      if (lo) launch_adjoint(a, ntiles_total, lds_adj, prec, gv, st);
     }
   }
 
-  void launch_round(hipStream_t st) {
+  void launch_round(hipStream_t st, int only = -1) {
     const StageArgs a = args();
+    const bool f32 = only < 0 || only == kFP32, lo = prec != kFP32 && (only < 0 || only == prec);
     launch_colnorm(a, nslice_total, (int)members.size(), st);
-    launch_adjoints(a, st);
+    launch_adjoints(a, st, only);
     launch_lstep(a, nlblk_total, st);
-    launch_forward(a, ntiles_total, lds_fwd, kFP32, 2, st);
-    if (prec != kFP32) launch_forward(a, ntiles_total, lds_fwd, prec, lp_rb, st);
+    if (f32) launch_forward(a, ntiles_total, lds_fwd, kFP32, 2, st);
+    if (lo) launch_forward(a, ntiles_total, lds_fwd, prec, lp_rb, st);
   }
 
   // one round with an event pair around each stage; returns after the events are read
@@ -595,6 +603,49 @@ struct Group {
       done += chunk;
     }
     for (; done < rounds; ++done) launch_round(st);
+    HIPCK(hipGetLastError());
+  }
+
+  // Rounds [r0, r0 + rounds) of a solve whose members all started at round 0 with the
+  // same max_iter and refresh_every (single and batch solves): round 0 runs the FP32
+  // initial forward, round r >= 1 iteration r, in FP32 when (r - 1) is a multiple of
+  // refresh_every or r >= max_iter (the refresh schedule of the column-norm kernel),
+  // in the reduced precision otherwise. The host therefore launches only the kernels
+  // of each round's precision; a kernel of the other precision would return at once,
+  // but its launch still costs several microseconds. Runs of rounds replay cached
+  // graphs. FP32 solves take run().
+  void run_aligned(int r0, int rounds, hipStream_t st, int max_iter, int refresh_every) {
+    if (prec == kFP32 || (prof && prof->on)) {
+      run(rounds, st, !(prof && prof->on), std::min(std::max(rounds, 1), 16));
+      return;
+    }
+    if (dirty) rebuild(st);
+    if (members.empty() || rounds <= 0) return;
+    auto kind = [&](int r) {
+      if (r == 0 || refresh_every <= 1 || r >= max_iter) return (int)kFP32;
+      return (r - 1) % refresh_every == 0 ? (int)kFP32 : prec;
+    };
+    int r = r0;
+    const int end = r0 + rounds;
+    while (r < end) {
+      const int kd = kind(r);
+      int n = 1;
+      while (r + n < end && kind(r + n) == kd && n < 16) ++n;
+      auto key = std::make_pair(kd, n);
+      auto it = kgraphs.find(key);
+      if (it == kgraphs.end()) {
+        hipGraph_t g;
+        hipGraphExec_t ge;
+        HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < n; ++i) launch_round(st, kd);
+        HIPCK(hipStreamEndCapture(st, &g));
+        HIPCK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+        HIPCK(hipGraphDestroy(g));
+        it = kgraphs.emplace(key, ge).first;
+      }
+      HIPCK(hipGraphLaunch(it->second, st));
+      r += n;
+    }
     HIPCK(hipGetLastError());
   }
 
@@ -966,13 +1017,13 @@ static icnnm_status do_solve(icnnm_ctx* c, const icnnm_shape* shape, const float
     std::vector<InstState> sts;
     while (ran < total) {
       const int chunk = std::min(10, total - ran);
-      g->run(chunk, st, true, 10);
+      g->run_aligned(ran, chunk, st, params->max_iter, params->refresh_every);
       ran += chunk;
       g->read_states(sts, st);
       if (sts[mb->slot].phase == kDone) break;
     }
   } else {
-    g->run(total, st, true, std::min(total, 16));
+    g->run_aligned(0, total, st, params->max_iter, params->refresh_every);
   }
   std::vector<InstState> sts;
   g->read_states(sts, st);
@@ -1035,7 +1086,7 @@ static icnnm_status do_solve_batch(icnnm_ctx* c, int count, const icnnm_shape* s
     std::vector<InstState> sts;
     while (ran < total) {
       const int chunk = std::min(10, total - ran);
-      g.run(chunk, st, true, 10);
+      g.run_aligned(ran, chunk, st, params->max_iter, params->refresh_every);
       ran += chunk;
       g.read_states(sts, st);
       bool all = true;
@@ -1043,7 +1094,7 @@ static icnnm_status do_solve_batch(icnnm_ctx* c, int count, const icnnm_shape* s
       if (all) break;
     }
   } else {
-    g.run(total, st, true, std::min(total, 16));
+    g.run_aligned(0, total, st, params->max_iter, params->refresh_every);
   }
   std::vector<InstState> sts;
   g.read_states(sts, st);

@@ -110,3 +110,38 @@ def test_batch_reduced_precision(lib):
     for p, L in zip(probs, Ls):
         Lo, _ = O.solve(p.M, p.mask, V32.astype(np.float64), kd, 40)
         assert _rel(L.cpu().numpy(), Lo) <= TOL_LP
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_stopping_checks_keep_the_refresh_schedule(lib, prec):
+    # tol > 0 runs the solve in chunks of rounds with a state read between them; a
+    # tolerance that never triggers must give bit for bit the result of tol = 0, with
+    # the FP32 refreshes (first iteration, every refresh_every-th, the last) in place
+    prob, V32 = _case((16, 16, 8), (4, 4, 4), 0.4, 7)
+    for iters, every in ((47, 10), (23, 4), (12, 1)):
+        print(f"[gpu] {prec} tol chunks iters={iters} refresh_every={every}", flush=True)
+        La, ia = lib.solve(_dev(prob.M), _dev(prob.mask), _dev(V32), prob.kdims, max_iter=iters, precision=prec,
+                           refresh_every=every)
+        Lb, ib = lib.solve(_dev(prob.M), _dev(prob.mask), _dev(V32), prob.kdims, max_iter=iters, precision=prec,
+                           refresh_every=every, tol=1e-30)
+        assert ia["iters"] == ib["iters"] == iters
+        assert np.array_equal(La.cpu().numpy(), Lb.cpu().numpy())
+    Lo, _ = O.solve(prob.M, prob.mask, V32.astype(np.float64), prob.kdims, 12)
+    assert _rel(Lb.cpu().numpy(), Lo) <= TOL_LP
+
+
+def test_batch_stopping_checks_keep_the_refresh_schedule(lib):
+    kd = (4, 4, 4)
+    probs = [inputs.random_problem(d, kd, 0.35, seed=80 + i) for i, d in enumerate([(16, 12, 8), (20, 9, 8), (8, 8, 8)])]
+    V, _ = O.learn([inputs.random_refs((16, 12, 8), 1, seed=90)[0]], kd)
+    V32 = V.astype(np.float32)
+    args = ([_dev(p.M) for p in probs], [_dev(p.mask) for p in probs], _dev(V32), kd)
+    print("[gpu] bf16 batch tol chunks", flush=True)
+    La, ia = lib.solve_batch(*args, max_iter=33, precision="bf16", refresh_every=7)
+    Lb, ib = lib.solve_batch(*args, max_iter=33, precision="bf16", refresh_every=7, tol=1e-30)
+    for p, a, b, x, y in zip(probs, La, Lb, ia, ib):
+        assert x["iters"] == y["iters"] == 33
+        a = a.cpu().numpy()
+        assert np.array_equal(a, b.cpu().numpy())
+        Lo, _ = O.solve(p.M, p.mask, V32.astype(np.float64), kd, 33)
+        assert _rel(a, Lo) <= TOL_LP

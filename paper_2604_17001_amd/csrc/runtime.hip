@@ -475,6 +475,10 @@ struct Group {
       lds_fwd = std::max(lds_fwd, lds_forward_floats(mb->plan, kp));
       lds_adj = std::max(lds_adj, lds_adjoint_floats(mb->plan, kp));
     }
+    // ICNNM_GATHER=generic keeps the position-owning gather everywhere (compares the
+    // two gathers; every plan's box fits both)
+    if (const char* e = getenv("ICNNM_GATHER"))
+      if (strcmp(e, "generic") == 0) gv = 0;
     ntiles_total = (int)tl.size();
     nlblk_total = (int)lb.size();
     nslice_total = (int)sl.size();

@@ -90,3 +90,32 @@ def test_concurrent_host_threads_on_one_context(lib):
     assert not errs, errs
     for a, b in zip(out, ref):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("kd", [(4, 4, 4), (8, 8, 4), (8, 16, 4)])
+def test_line_gather_equals_position_gather(prec, kd, monkeypatch):
+    # the line-owning col2im gather (innermost kernel extent 4, innermost tile extent 8)
+    # adds every box position's terms in the same order as the position-owning one, so
+    # the two give identical sums; k = 64 runs the per-unit adjoint, k = 256 and 512 the
+    # tiled one. Fresh contexts with a forced 4x4x8 tile box that admits the line gather.
+    from paper_2604_17001_amd import icnnm
+    dims = (32, 32, 16)
+    prob, V32 = _case(dims, kd, 50 + kd[1])
+    E = [4 + kd[0] - 1, 4 + kd[1] - 1, 8 + kd[2] - 1]
+    assert kd[2] == 4 and E[0] * E[1] <= 512  # the line gather applies
+    monkeypatch.setenv("ICNNM_TILE", "4,4,8")
+    outs = []
+    for gather in (None, "generic"):
+        if gather:
+            monkeypatch.setenv("ICNNM_GATHER", gather)
+        print(f"[gpu] gather {gather or 'lines'} {prec} kd={kd}", flush=True)
+        solo = icnnm.Library()
+        try:
+            L, info = solo.solve(_dev(prob.M), _dev(prob.mask), _dev(V32), kd, max_iter=20, precision=prec)
+        finally:
+            solo.close()
+        assert tuple(info["tile"]) == (4, 4, 8)
+        outs.append((L.cpu().numpy(), info["objective"]))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1] == outs[1][1]

@@ -52,3 +52,9 @@ def test_batch_stops_each_instance_on_its_own(lib):
         Lo, _ = O.solve(p.M, p.mask, V32.astype(np.float64), kd, info["iters"])
         assert np.linalg.norm(L.cpu().numpy() - Lo) / np.linalg.norm(Lo) <= 1e-5
     assert len(set(its)) > 1  # the instances really stopped at different iterations
+
+
+def test_empty_batch(lib):
+    _, V32, kd = _setup()
+    Ls, infos = lib.solve_batch([], [], _dev(V32), kd, max_iter=10)
+    assert Ls == [] and infos == []

@@ -53,6 +53,8 @@ CASES = [
     ((24, 24, 8), (8, 8, 8), 0.4, 7),      # k = 512: the tiled large-kernel adjoint
     ((20, 18, 12), (6, 6, 9), 0.4, 8),     # k = 324 padded to 512, ragged tiles
     ((16, 16, 16), (16, 16, 4), 0.5, 9),   # k = 1024, the 16x16x4 kernel
+    ((10, 9, 6), (1, 1, 1), 0.4, 10),      # k = 1: a one-entry kernel
+    ((8, 6, 4), (8, 6, 4), 0.4, 11),       # kernel as large as the tensor (k = m = 192)
 ]
 
 

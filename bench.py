@@ -33,10 +33,10 @@ METRIC = "solved tensors/s at rel.err\u22641e-3 vs FP64 oracle; p50/p99 latency;
 # the same counters on a plain 256 MiB copy (fetch x2.0, write x1.0); valid only for the
 # kernel source they were taken on (sha256 prefix of kernels.hip)
 TRAFFIC = {
-    ("64x64x16", "fp32", "forward"): {"bytes": 284.9e6, "src": "9d7d44ca35f0343c"},
-    ("64x64x16", "fp32", "adjoint"): {"bytes": 139.5e6, "src": "9d7d44ca35f0343c"},
-    ("128x128x32", "bf16", "forward"): {"bytes": 10.09e9, "src": "9d7d44ca35f0343c"},
-    ("128x128x32", "bf16", "adjoint"): {"bytes": 5.64e9, "src": "9d7d44ca35f0343c"},
+    ("64x64x16", "fp32", "forward"): {"bytes": 284.7e6, "src": "0331dca4bd7903ee"},
+    ("64x64x16", "fp32", "adjoint"): {"bytes": 139.3e6, "src": "0331dca4bd7903ee"},
+    ("128x128x32", "bf16", "forward"): {"bytes": 9.86e9, "src": "0331dca4bd7903ee"},
+    ("128x128x32", "bf16", "adjoint"): {"bytes": 5.63e9, "src": "0331dca4bd7903ee"},
 }
 
 

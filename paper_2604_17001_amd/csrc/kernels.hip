@@ -5,9 +5,11 @@
 //   A_k^*(X)[t]  = sum_s X[(t + s) mod m, s]   its adjoint
 // The m x k state arrays (scaled dual U and Q = W - U) are stored in "tile
 // layout": for each 32-row group of a tile and each 32-column block, the 1024
-// values sit in the order of the 32x32 MFMA accumulator, lane-major, so a lane
-// reads and writes its 16 values as four 16-byte accesses and the adjoint
-// consumes them directly as its B operand without a transpose.
+// values are the 32x32 MFMA accumulator's, as 256 float4: float4 g (accumulator
+// values 4g..4g+3) of lane l at position g * 64 + l. A lane reads and writes its
+// 16 values as four 16-byte accesses, each of which is one contiguous kilobyte
+// over the wavefront, and the adjoint consumes them directly as its B operand
+// without a transpose.
 //
 // Accumulator layout of v_mfma_f32_32x32x2_f32 for D = A(32 x 2) B(2 x 32):
 //   lane l, register v holds D[(v/4)*8 + (l/32)*4 + v%4][l%32];
@@ -514,13 +516,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
     float4 bu[kAhead][4], bq[kAhead][4];
     auto load_piece = [&](int pc, int slot) {
       const int cb = pc / RB, ib = pc % RB;
-      const size_t sidx = ((((size_t)lt * (I.bm / 32) + ru * RB + ib) * nkb + c0 / 32 + cb) * 64 + lane) * 4;
+      const size_t sidx = (((size_t)lt * (I.bm / 32) + ru * RB + ib) * nkb + c0 / 32 + cb) * 256 + lane;
       gcfloat4* Up = gc4(I.U) + sidx;
       gcfloat4* Qp = gc4(I.Q) + sidx;
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        bu[slot][g] = Up[g];
-        bq[slot][g] = Qp[g];
+        bu[slot][g] = Up[g * 64];
+        bq[slot][g] = Qp[g * 64];
       }
     };
     // Two compiled forms of the same arithmetic: the first forward of a solve (U = 0,
@@ -561,7 +563,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
           if constexpr (!kFirst) {
             if (pc + kAhead < kPieces) load_piece(pc + kAhead, slot);
           }
-          const size_t sidx = ((((size_t)lt * (I.bm / 32) + ru * RB + ib) * nkb + cblk) * 64 + lane) * 4;
+          const size_t sidx = (((size_t)lt * (I.bm / 32) + ru * RB + ib) * nkb + cblk) * 256 + lane;
           gfloat4* Up = g4(I.U) + sidx;
           gfloat4* Qp = g4(I.Q) + sidx;
 #pragma unroll
@@ -606,8 +608,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
               qs[4 * g + e] += qnew * qnew;
               ws[4 * g + e] += w * w;
             }
-            Up[g] = make_float4(un[0], un[1], un[2], un[3]);
-            Qp[g] = make_float4(qn[0], qn[1], qn[2], qn[3]);
+            Up[g * 64] = make_float4(un[0], un[1], un[2], un[3]);
+            Qp[g * 64] = make_float4(qn[0], qn[1], qn[2], qn[3]);
           }
           // FP32: one piece at a time (keeps the scheduler from hoisting the loads of
           // later pieces, which costs registers)
@@ -861,11 +863,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
       const int cb = h >> 1, p = h & 1;
 #pragma unroll
       for (int jb = 0; jb < 2; ++jb) {
-        const size_t o = (row0 + (size_t)jb * nkb + cb) * 256 + lane * 4 + 2 * p;
+        const size_t o = (row0 + (size_t)jb * nkb + cb) * 256 + 2 * p * 64 + lane;
         fu[jb][0] = U4[o];
-        fu[jb][1] = U4[o + 1];
+        fu[jb][1] = U4[o + 64];
         fq[jb][0] = Q4[o];
-        fq[jb][1] = Q4[o + 1];
+        fq[jb][1] = Q4[o + 64];
       }
       fs[0] = *gc4(S + cb * 32 + (2 * p) * 8 + half * 4);
       fs[1] = *gc4(S + cb * 32 + (2 * p + 1) * 8 + half * 4);
@@ -916,11 +918,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
       const int cb = h >> 1, p = h & 1;
 #pragma unroll
       for (int jb = 0; jb < 2; ++jb) {
-        const size_t o = (row0 + (size_t)jb * nkb + cb) * 256 + lane * 4 + 2 * p;
+        const size_t o = (row0 + (size_t)jb * nkb + cb) * 256 + 2 * p * 64 + lane;
         fu[jb][0] = U4[o];
-        fu[jb][1] = U4[o + 1];
+        fu[jb][1] = U4[o + 64];
         fq[jb][0] = Q4[o];
-        fq[jb][1] = Q4[o + 1];
+        fq[jb][1] = Q4[o + 64];
       }
       fs[0] = *gc4(S + cb * 32 + (2 * p) * 8 + half * 4);
       fs[1] = *gc4(S + cb * 32 + (2 * p + 1) * 8 + half * 4);
@@ -1015,11 +1017,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big(StageArgs a) {
   float4 cu[2][2], cq[2][2], cs[2][2], cv[2][4];  // [slot][...]
   auto coop_load = [&](int q, int sl) {
     const int cb = q >> 1, p = q & 1;
-    const size_t o = (((size_t)lt * 4 + rg) * nkb + cb) * 256 + lane * 4 + 2 * p;
+    const size_t o = (((size_t)lt * 4 + rg) * nkb + cb) * 256 + 2 * p * 64 + lane;
     cu[sl][0] = U4[o];
-    cu[sl][1] = U4[o + 1];
+    cu[sl][1] = U4[o + 64];
     cq[sl][0] = Q4[o];
-    cq[sl][1] = Q4[o + 1];
+    cq[sl][1] = Q4[o + 64];
     cs[sl][0] = *gc4(I.s + cb * 32 + (2 * p) * 8 + hf * 4);
     cs[sl][1] = *gc4(I.s + cb * 32 + (2 * p + 1) * 8 + hf * 4);
     gcfloat4* vp = gc4(vrow + q * kBigChunk);
@@ -1139,20 +1141,23 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
   const float rp = (float)(1.0 / I.st->ratio_prev);
   const int rg = tid >> 6, hf = (tid >> 5) & 1;
   // thread t stages G of (row group t/64, lane t%64) of the tile layout (16 values)
-  // and the 32 halves of V row s = t of this offset group
-  gcfloat4* vrow = gc4(a.Vp_lo) + (size_t)(sg * kGroup + tid) * (kp / 8);
+  // and a quarter (16 bytes) of four V rows of this offset group: instruction i of
+  // wavefront w covers rows w * 64 + 16 i .. + 15 whole, 64 contiguous bytes each
+  const int vr = wave * 64 + (lane >> 2), vf = lane & 3;
+  gcfloat4* vrow = gc4(a.Vp_lo) + (size_t)(sg * kGroup + vr) * (kp / 8) + vf;
+  const size_t vstep = (size_t)16 * (kp / 8);
   float4 cu[4], cq[4], cv0, cv1, cv2, cv3;
   auto coop_load = [&](int cb) {
-    const size_t o = (((size_t)lt * 4 + rg) * nkb + cb) * 256 + lane * 4;
+    const size_t o = (((size_t)lt * 4 + rg) * nkb + cb) * 256 + lane;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-      cu[g] = U4[o + g];
-      cq[g] = Q4[o + g];
+      cu[g] = U4[o + g * 64];
+      cq[g] = Q4[o + g * 64];
     }
-    cv0 = vrow[cb * 4 + 0];
-    cv1 = vrow[cb * 4 + 1];
-    cv2 = vrow[cb * 4 + 2];
-    cv3 = vrow[cb * 4 + 3];
+    cv0 = vrow[cb * 4];
+    cv1 = vrow[vstep + cb * 4];
+    cv2 = vrow[2 * vstep + cb * 4];
+    cv3 = vrow[3 * vstep + cb * 4];
   };
   auto coop_store = [&](int buf, int cb) {
     // value v = 4g + e of the tile layout sits at column acc_col(v, hf) = 8g + 4hf + e
@@ -1167,11 +1172,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
       t[3] = (H)((sv.w - 1.f) * cq[g].w - cu[g].w * rp);
       *reinterpret_cast<V4*>(gd + 8 * g) = t;
     }
-    float4* vd = reinterpret_cast<float4*>(Vs + ((size_t)buf * 256 + tid) * kBigLpPad);
+    float4* vd = reinterpret_cast<float4*>(Vs + ((size_t)buf * 256 + vr) * kBigLpPad) + vf;
+    const int rs = 16 * kBigLpPad / 8;  // float4s per 16 rows
     vd[0] = cv0;
-    vd[1] = cv1;
-    vd[2] = cv2;
-    vd[3] = cv3;
+    vd[rs] = cv1;
+    vd[2 * rs] = cv2;
+    vd[3 * rs] = cv3;
   };
   coop_load(0);
   __syncthreads();

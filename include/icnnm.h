@@ -33,7 +33,11 @@
  *    ICNNM_AUTOTUNE=1 by timing the best few candidates on the instance (solve
  *    and solve_batch; cached per shape in the context and, if
  *    ICNNM_AUTOTUNE_CACHE names a file, across processes). icnnm_info.tile
- *    reports the box used.
+ *    reports the box used. Two switches exist for measurement:
+ *    ICNNM_TILE=b0,b1,b2 forces one box (ICNNM_E_INVALID if it does not fit
+ *    the problem; a different box changes the floating-point summation order,
+ *    so results agree to rounding, not bit for bit), and ICNNM_GATHER=generic
+ *    keeps the position-owning col2im gather (bit-identical results).
  *  - Thread safety: a context may be used from several host threads; calls
  *    on one context are serialised internally. icnnm_submit/icnnm_poll may be
  *    called concurrently with each other.

@@ -10,7 +10,13 @@ generators; nothing here touches the GPU library. For each workload it stores
   (float64), computed from the float32 inputs upcast to float64;
 * ``<name>_meta.json`` - iterations, theta0, residuals, objective, timings.
 
-Usage: python tests/golden/make_golden.py 16x16x8 64x64x16 [128x128x32]
+For the uneven 64-instance batch (``batch``) it stores the oracle-learned V of
+the workload's 20 references (``batch_V.npy``) and, for the instances listed in
+``BATCH_GOLDEN`` (chosen to span the 48 and 96 extents, 8, 16 and 32 frames and
+all three mask types), ``batch_<idx>_L.npy`` after the workload's 200
+iterations, plus ``batch_meta.json``.
+
+Usage: python tests/golden/make_golden.py 16x16x8 64x64x16 [128x128x32] [batch]
 """
 import json
 import os
@@ -30,7 +36,36 @@ WORKLOADS = {"16x16x8": inputs.prediction_16x16x8, "64x64x16": inputs.video_64x6
              "128x128x32": inputs.interpolation_128x128x32}
 
 
+# batch instances with stored oracle results: index -> (dims, mask type) as drawn
+BATCH_GOLDEN = (2, 1, 16, 49, 29, 24, 3)
+
+
+def make_batch():
+    wl = inputs.batch_uneven()
+    t0 = time.time()
+    V, w = O.learn(wl.refs, wl.kdims)
+    V32 = V.astype(np.float32)
+    np.save(os.path.join(HERE, "batch_V.npy"), V32)
+    meta = {"workload": wl.name, "kdims": list(wl.kdims), "iters": wl.iters, "refs": len(wl.refs),
+            "eig_top": [float(x) for x in w[:4]], "learn_s": time.time() - t0, "instances": {}}
+    print("batch V", json.dumps(meta), flush=True)
+    for idx in BATCH_GOLDEN:
+        p = wl.problems[idx]
+        t1 = time.time()
+        L, info = O.solve(p.M, p.mask, V32.astype(np.float64), wl.kdims, wl.iters)
+        np.save(os.path.join(HERE, f"batch_{idx}_L.npy"), L)
+        meta["instances"][str(idx)] = {"dims": list(p.dims), "mask_kind": p.meta["mask_kind"],
+                                       "iters": info["iters"], "theta0": info["theta0"],
+                                       "r_primal": info["r_primal"], "r_change": info["r_change"],
+                                       "objective": info["objective"], "solve_s": time.time() - t1}
+        print(idx, json.dumps(meta["instances"][str(idx)]), flush=True)
+        with open(os.path.join(HERE, "batch_meta.json"), "w") as f:
+            json.dump(meta, f, indent=1)
+
+
 def make(name):
+    if name == "batch":
+        return make_batch()
     wl = WORKLOADS[name]()
     prob = wl.problems[0]
     t0 = time.time()

@@ -8,6 +8,8 @@
 * eq:cnnorm: with K learned from L itself, ||A_k(L)K||_{2,1} = ||A_k(L)||_*.
 * For any orthogonal K, ||A_k(L)K||_{2,1} >= ||A_k(L)||_*, and K = I gives k||L||_F.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -108,3 +110,36 @@ def test_ground_truth_eigenvectors_have_unit_alpha():
     assert abs(O.spectral_correlation(L0, V, kdims) - 1.0) < 1e-9
     r0 = int(np.linalg.matrix_rank(O.conv_matrix(L0, kdims), tol=1e-8))
     assert O.relative_rank(L0, V, kdims) == r0 == 4
+
+
+def _fft_conv(L, X):
+    """Circular convolution L * X by the convolution theorem, X zero-padded to L's shape."""
+    Xp = np.zeros(L.shape)
+    Xp[tuple(slice(0, k) for k in X.shape)] = X
+    return np.real(np.fft.ifftn(np.fft.fftn(L) * np.fft.fftn(Xp)))
+
+
+@pytest.mark.parametrize("dims,kdims", [((8, 6, 5), (3, 2, 2)), ((10, 7), (4, 3))])
+def test_relative_eigenvalues_by_fft_convolution(dims, kdims):
+    """Definition 2: sigma^K_i = ||L0 * kappa_i||_F, here with the convolution done by
+    FFT and kappa_i the i-th column of V reshaped to the kernel."""
+    g = np.random.default_rng(15)
+    L0 = g.standard_normal(dims)
+    V, _ = O.learn(_refs(dims, 3, 16), kdims)
+    want = np.array([np.linalg.norm(_fft_conv(L0, V[:, i].reshape(kdims))) for i in range(V.shape[1])])
+    np.testing.assert_allclose(O.relative_eigs(L0, V, kdims), want, rtol=1e-11, atol=1e-12 * want.max())
+
+
+def test_spectral_correlation_by_autocorrelation_gram():
+    """eq:alphaK: alpha_K^2 is the largest eigenvalue of D V^T G V D, with G the Gram of
+    A_k(L0) built from the FFT autocorrelation and D = diag(1/sigma^K_i) on the support."""
+    dims, kdims = (8, 6, 5), (3, 2, 2)
+    g = np.random.default_rng(17)
+    L0 = g.standard_normal(dims)
+    V, _ = O.learn(_refs(dims, 3, 18), kdims)
+    C = V.T @ _autocorr_gram([L0], kdims) @ V
+    s = np.sqrt(np.diag(C))
+    d = 1.0 / s
+    alpha = math.sqrt(float(np.linalg.eigvalsh(C * np.outer(d, d)).max()))
+    assert abs(O.spectral_correlation(L0, V, kdims) - alpha) < 1e-10 * alpha
+    assert O.relative_rank(L0, V, kdims) == V.shape[1]

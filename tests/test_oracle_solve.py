@@ -188,3 +188,46 @@ def test_stopping_rule():
     L, info = O.solve(M, mask, V, kdims, 1000, tol=1e-4)
     assert info["converged"] and info["iters"] < 1000
     assert max(info["r_primal"], info["r_change"]) <= 1e-4
+
+
+def test_penalized_objective_hand_value():
+    """eq:admm on a 3 x 2 tensor with a 2 x 1 kernel (k = 2) and K = I, by hand.
+
+    L has a single 1 at (0, 0), so both columns of A_k(L) (L and L shifted by one
+    row) have norm 1 and ||A_k(L)I||_{2,1} = 2. Observed entries (0,0), (1,0), (2,1)
+    with M values 3, 1, 2 give L - M = -2, -1, -2 there, ||P_Omega(L - M)||^2 = 9,
+    and the penalty (lambda k / 2) * 9 = 9 lambda: 9002 for lambda = 1000.
+    """
+    L = np.array([[1.0, 0.0], [0.0, 0.0], [0.0, 0.0]])
+    M = np.array([[3.0, 7.0], [1.0, 7.0], [7.0, 2.0]])
+    mask = np.array([[1, 0], [1, 0], [0, 1]], dtype=np.uint8)
+    V = np.eye(2)
+    assert O.objective(L, V, (2, 1)) == 2.0
+    assert O.objective(L, V, (2, 1), M, mask, 1000.0) == 9002.0
+    assert O.objective(L, V, (2, 1), M, mask, 0.5) == 2.0 + 4.5
+
+
+@pytest.mark.parametrize("lam", [2.0, 50.0])
+def test_penalized_solution_minimizes_objective(lam):
+    """The ADMM limit of the penalized program (whose L-step is the paper's closed
+    form) is a minimizer of objective(): no perturbation lowers it. A wrong
+    weight of the penalty term in objective() moves its minimizer away."""
+    dims, kdims = (5, 4, 3), (2, 2, 2)
+    M, mask, V, _ = _problem(dims, kdims, 0.5, seed=8, b=4)
+    L, _ = O.solve(M, mask, V, kdims, 600, lam=lam)
+    f0 = O.objective(L, V, kdims, M, mask, lam)
+    g = np.random.default_rng(9)
+    eps = 1e-3 * np.linalg.norm(L) / math.sqrt(L.size)
+    for _ in range(20):
+        E = g.standard_normal(dims)
+        E *= eps / np.linalg.norm(E) * math.sqrt(L.size)
+        assert O.objective(L + E, V, kdims, M, mask, lam) >= f0 - 1e-9 * f0
+    # the same check fails for a doubled penalty weight (what a dropped 1/2 would give)
+    twice = lambda X: O.objective(X, V, kdims) + lam * int(np.prod(kdims)) * float(
+        np.sum(O.project(X - M, mask) ** 2))
+    lower = 0
+    for _ in range(20):
+        E = g.standard_normal(dims)
+        E *= eps / np.linalg.norm(E) * math.sqrt(L.size)
+        lower += twice(L + E) < twice(L) or twice(L - E) < twice(L)
+    assert lower > 0

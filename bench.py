@@ -1,17 +1,25 @@
 """Benchmark of the ICNNM solver on one MI355X.
 
-A step is one complete solve (every ADMM iteration of Section III-D: column
-norms and shrinkage, adjoint with col2im, L-step with P_Omega, forward
-contraction with the fused dual update) of one synthetic tensor. The default
-workload is the 64x64x16 video-shaped tensor with an 8x8x4 kernel (k = 256),
-30% random plus 8x8 block missing entries, 200 iterations, FP32. The metric
-is solved tensors per second with inputs resident in HBM.
+Default (the headline): the batching form in BF16. A step is one complete solve
+(200 ADMM iterations of Section III-D: column norms and shrinkage, adjoint with
+col2im, L-step with P_Omega, forward contraction with the fused dual update) of
+the uneven 64-instance batch (spatial extents {32,48,64,96,128}^2, 8/16/32
+frames, three mask types, 8x8x4 kernel, one shared V), with both contractions
+on BF16 MFMA (FP32 accumulate) and an FP32 refresh every 10 iterations. The
+value is solved tensors per second with inputs resident in HBM.
 
-Prints one JSON line with the throughput, per-solve latency percentiles, the
-relative error against the stored FP64 oracle result, a roofline entry for
-the dominant kernel (stage durations measured with HIP events on the
-library's stream in a separate profiled pass) and the FP64 oracle's own rate
-on a bounded sample of the same workload on the host cores.
+Beside it, on the same JSON line: the error of the batch's results against the
+stored FP64 oracle results of seven instances; the plain FP32 per-instance
+solver, one instance at a time, on the same 64 instances (rate and error); a
+short served stream (Poisson arrivals, mixed sizes, 10% 128x128x32 requests at
+k = 1024) with arrival-to-retirement p50/p99; a roofline entry for the dominant
+reduced-precision kernel (stage durations measured with HIP events on the
+library's stream in a profiled pass after the timed one); the 64x64x16 FP32
+single-instance form; and the FP64 oracle's rate on a bounded sample on the
+host cores.
+
+Other forms: --workload 16x16x8 | 64x64x16 | 128x128x32 (single instances),
+--workload serve (a full serving sweep point).
 """
 from __future__ import annotations
 
@@ -46,6 +54,36 @@ def _kernel_src_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+def _gold(name):
+    return os.path.join(ROOT, "tests", "golden", name)
+
+
+def _host_info():
+    """CPU model, BLAS library and its thread count (for the oracle baseline)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas, threads = "unknown", os.cpu_count()
+    try:
+        import numpy as _np
+        from threadpoolctl import threadpool_info
+        _np.ones((4, 4)) @ _np.ones((4, 4))
+        for i in threadpool_info():
+            if i.get("user_api") == "blas":
+                blas = f"{i.get('internal_api')} {i.get('version')}"
+                threads = i.get("num_threads", threads)
+                break
+    except Exception:  # pragma: no cover
+        pass
+    return model, blas, int(threads)
+
+
 def _workload(name):
     from paper_2604_17001_amd import inputs
     return {"16x16x8": inputs.prediction_16x16x8, "64x64x16": inputs.video_64x64x16,
@@ -60,23 +98,64 @@ def _count_tiles(infos):
     return out
 
 
-def _batch_main(args):
-    """Batching form: 64 uneven instances (extents {32..128}^2 x {8,16,32}, 8x8x4 kernel,
-    one shared V) solved in joint launches; a step is one solve of the whole batch."""
+def _stage_avgs(st):
+    """Average duration (us) per launch of each (stage, precision part) that ran."""
+    return {f"{name}_{part}": {"avg_us": round(1e3 * ms / n, 3), "launches": n}
+            for (name, part), (ms, n) in st.items() if n > 0}
+
+
+def _roofline(kernel, avg_us, flops, abytes, precision, traffic=None):
+    """Roofline entry of one kernel: MFMA-bound when its intensity (FLOP per byte of
+    algorithmic traffic) is above the ridge point of its precision, HBM-bound below."""
+    mpeak = PEAKS["fp32_mfma"] if precision == "fp32" else PEAKS[f"{precision}_mfma"]
+    sec = avg_us * 1e-6
+    tflops = flops / sec / 1e12
+    if flops / abytes >= mpeak * 1e12 / (PEAKS["hbm_gbs"] * 1e9):
+        return {"bound": "mfma", "kernel": kernel, "achieved": round(tflops, 3), "peak": mpeak, "unit": "TFLOP/s",
+                "frac": round(tflops / mpeak, 4), "traffic": traffic, "flops_per_launch": flops,
+                "algorithmic_bytes_per_launch": abytes, "avg_us": round(avg_us, 3)}
+    gbs = abytes / sec / 1e9
+    return {"bound": "hbm", "kernel": kernel, "achieved": round(gbs, 1), "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
+            "frac": round(gbs / PEAKS["hbm_gbs"], 4), "traffic": traffic, "algorithmic_bytes_per_launch": abytes,
+            "flops_per_launch": flops, "mfma_tflops": round(tflops, 3), "mfma_frac": round(tflops / mpeak, 4),
+            "avg_us": round(avg_us, 3)}
+
+
+def _padded_k(k):
+    return ((k + 63) // 64) * 64 if k <= 256 else ((k + 255) // 256) * 256
+
+
+def _headline(args):
+    """Batching form in BF16 (the metric's subject) beside the plain FP32 solver one
+    instance at a time, a short served stream, the 64x64x16 FP32 single-instance form
+    and the oracle's CPU rate."""
     import torch
     from paper_2604_17001_amd import icnnm
     if not args.no_autotune:
-        # tile boxes measured per instance shape during the untimed warm-up
-        os.environ["ICNNM_AUTOTUNE"] = "1"
+        os.environ["ICNNM_AUTOTUNE"] = "1"   # tile boxes measured during the untimed warm-up
+    prec = args.precision or "bf16"
     wl = _workload("batch")
     iters = args.iters or wl.iters
+    meta = json.load(open(_gold("batch_meta.json")))
     lib = icnnm.Library.get()
     dev = torch.device("cuda", 0)
     Ms = [torch.from_numpy(p.M).to(dev) for p in wl.problems]
     masks = [torch.from_numpy(p.mask).to(dev) for p in wl.problems]
     outs = [torch.empty_like(x) for x in Ms]
-    V, _ = lib.learn_eigvecs([torch.from_numpy(r).to(dev) for r in wl.refs], wl.kdims)
-    kw = dict(max_iter=iters, precision=args.precision)
+    # pre-step (not timed in the metric): V learned on the GPU from the 20 references;
+    # the solves use the oracle-learned V stored with the oracle results (the same
+    # float32 V on both sides, so the error is the solver's alone)
+    torch.cuda.synchronize()
+    t_l = time.perf_counter()
+    lib.learn_eigvecs([torch.from_numpy(r).to(dev) for r in wl.refs], wl.kdims)
+    torch.cuda.synchronize()
+    learn_s = time.perf_counter() - t_l
+    V = torch.from_numpy(np.ascontiguousarray(np.load(_gold("batch_V.npy")))).to(dev)
+    n = len(wl.problems)
+    msum = sum(p.m for p in wl.problems)
+    k = wl.problems[0].k
+    kw = dict(max_iter=iters, precision=prec)
+    print(f"[bench] batch {n} instances, {prec}, warm-up", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         lib.solve_batch(Ms, masks, V, wl.kdims, outs=outs, **kw)
     torch.cuda.synchronize()
@@ -88,33 +167,187 @@ def _batch_main(args):
         lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    n = len(wl.problems)
-    msum = sum(p.m for p in wl.problems)
-    # one-at-a-time FP32 solves of the same instances, the baseline form (one untimed
-    # pass first: per-shape set-up and, with autotuning, tile measurement)
-    for M, mk, o in zip(Ms, masks, outs):
+    value = n * args.steps / dt
+    print(f"[bench] batch {prec}: {value:.3f} tensors/s", file=sys.stderr, flush=True)
+
+    def errs(Ls):
+        out = {}
+        if iters != meta["iters"]:
+            return out
+        for idx in meta["instances"]:
+            ref = np.load(_gold(f"batch_{idx}_L.npy"))
+            L = Ls[int(idx)].cpu().numpy().astype(np.float64)
+            out[idx] = float(np.linalg.norm(L - ref) / np.linalg.norm(ref))
+        return out
+    e_batch = errs(outs)
+
+    # plain FP32 per-instance solver, one instance at a time, on the same instances
+    # (one untimed pass first: per-shape set-up and, with autotuning, tile measurement)
+    outs32 = [torch.empty_like(x) for x in Ms]
+    for M, mk, o in zip(Ms, masks, outs32):
         lib.solve(M, mk, V, wl.kdims, out=o, max_iter=iters)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for M, mk, o in zip(Ms, masks, outs):
+    for M, mk, o in zip(Ms, masks, outs32):
         lib.solve(M, mk, V, wl.kdims, out=o, max_iter=iters)
     torch.cuda.synchronize()
-    single = n / (time.perf_counter() - t1)
-    flops = 4.0 * msum * wl.problems[0].k ** 2 * iters
-    out = {"metric": "solved tensors/s (uneven batch) at rel.err<=1e-3 vs FP64 oracle",
-           "value": round(n * args.steps / dt, 3), "unit": "tensors/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else args.precision,
-           "data": "synthetic",
-           "config": {"workload": wl.name, "instances": n, "sum_m": msum, "kdims": list(wl.kdims),
-                      "iters": iters, "precision": args.precision, "autotune": not args.no_autotune},
-           "tiles": {k: v for k, v in sorted(_count_tiles(infos).items())},
-           "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
-           "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
-           "tflops_effective": round(flops * args.steps / dt / 1e12, 2),
-           "fp32_one_at_a_time_tensors_per_s": round(single, 3),
-           "iters_run": [i["iters"] for i in infos][:4]}
+    plain = n / (time.perf_counter() - t1)
+    e_plain = errs(outs32)
+    print(f"[bench] plain fp32 one at a time: {plain:.3f} tensors/s", file=sys.stderr, flush=True)
+
+    # per-kernel durations: one profiled batch solve (HIP events around every launch)
+    roofline, stages = None, None
+    if not args.no_profile:
+        lib.stage_times(reset=True)
+        lib.set_profiling(True)
+        lib.solve_batch(Ms, masks, V, wl.kdims, outs=outs, **kw)
+        lib.set_profiling(False)
+        stages = _stage_avgs(lib.stage_times(reset=True, split=True))
+        kp = _padded_k(k)
+        part = "lowp" if prec != "fp32" else "fp32"
+        cand = {"forward": 16.0 * msum * kp, "adjoint": 8.0 * msum * kp}
+        dom = max(cand, key=lambda s: stages.get(f"{s}_{part}", {"avg_us": 0.0})["avg_us"])
+        tr = TRAFFIC.get(("batch", prec, dom))
+        traffic = tr["bytes"] if tr and tr["src"] == _kernel_src_hash() and iters == wl.iters else None
+        roofline = _roofline(f"{dom}_{part}", stages[f"{dom}_{part}"]["avg_us"], 2.0 * msum * k * k, cand[dom],
+                             prec, traffic)
+
+    serving = None if args.no_serve else _serve_leg(args)
+    other = None if args.no_compare else _single_fp32_leg(args)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = _cpu_baseline_batch(wl, np.load(_gold("batch_V.npy")), iters, args.cpu_sample_iters, msum)
+
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3), "unit": "tensors/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": prec if prec != "fp32" else "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "instances": n, "sum_m": msum, "kdims": list(wl.kdims), "k": k,
+                   "iters": iters, "precision": prec, "refresh_every": 10, "lambda": "inf",
+                   "autotune": not args.no_autotune, "step": "one solve of the whole batch"},
+        "p50_ms": round(float(np.percentile(lat_ms, 50)), 3), "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+        "rel_err_vs_oracle": max(e_batch.values()) if e_batch else None,
+        "rel_err_by_instance": {i: float(f"{v:.3e}") for i, v in e_batch.items()},
+        "plain_fp32_one_at_a_time": {"value": round(plain, 3), "unit": "tensors/s",
+                                     "rel_err_vs_oracle": max(e_plain.values()) if e_plain else None},
+        "vs_plain_fp32": round(value / plain, 3),
+        "tiles": {kk: v for kk, v in sorted(_count_tiles(infos).items())},
+        "learn_s": round(learn_s, 3),
+        "roofline": roofline, "stages": stages, "serving": serving, "other_form": other, "cpu_baseline": cpu,
+    }
     print(json.dumps(out), flush=True)
+
+
+def _serve_leg(args):
+    """A short served stream: Poisson arrivals of batch-type requests and 10%
+    128x128x32 requests at k = 1024, BF16, each retired at residual <= 1e-4.
+    Latency is arrival to retirement; only requests that returned OK count."""
+    import torch
+    from paper_2604_17001_amd import icnnm, inputs
+    rate, n = args.serve_rate, args.serve_requests
+    print(f"[bench] serving leg: {n} requests at {rate} req/s", file=sys.stderr, flush=True)
+    arrivals, probs = inputs.serve_requests(n, rate, large_frac=0.10)
+    lib = icnnm.Library(budget=int(args.budget_gb * (1 << 30)))
+    dev = torch.device("cuda", 0)
+    try:
+        banks = {}
+        for kd, gen in [((8, 8, 4), inputs.batch_uneven), ((16, 16, 4), inputs.interpolation_128x128x32)]:
+            if any(tuple(p.kdims) == kd for p in probs):
+                refs = gen(b_refs=4).refs if kd == (16, 16, 4) else gen(count=1).refs
+                banks[kd] = lib.learn_eigvecs([torch.from_numpy(r).to(dev) for r in refs], kd)[0]
+        Ms = [torch.from_numpy(p.M).to(dev) for p in probs]
+        masks = [torch.from_numpy(p.mask).to(dev) for p in probs]
+        outs = [torch.empty_like(x) for x in Ms]
+        torch.cuda.synchronize()
+        kw = dict(max_iter=1000, tol=1e-4, precision="bf16")
+        t0 = time.perf_counter()
+        tickets, done, t_ret, iters = {}, {}, {}, {}
+        nxt = 0
+        while len(done) < n:
+            now = time.perf_counter() - t0
+            while nxt < n and arrivals[nxt] <= now:
+                p = probs[nxt]
+                tickets[lib.submit(Ms[nxt], masks[nxt], banks[tuple(p.kdims)], p.kdims, outs[nxt], **kw)] = nxt
+                nxt += 1
+            for t, i in list(tickets.items()):
+                rc, info = lib.poll(t)
+                if rc != icnnm.PENDING:
+                    done[i] = rc
+                    t_ret[i] = time.perf_counter() - t0
+                    iters[i] = info["iters"]
+                    del tickets[t]
+            time.sleep(0.0005)
+    finally:
+        lib.close()
+    ok = [i for i in range(n) if done[i] == icnnm.OK]
+    if not ok:
+        return {"requests": n, "ok": 0}
+    window = max(t_ret[i] for i in ok) - arrivals[0]
+    lat_ms = np.array([t_ret[i] - arrivals[i] for i in ok]) * 1e3
+    return {"rate_req_s": rate, "requests": n, "ok": len(ok), "tensors_per_s": round(len(ok) / window, 3),
+            "p50_ms": round(float(np.percentile(lat_ms, 50)), 2), "p99_ms": round(float(np.percentile(lat_ms, 99)), 2),
+            "mean_iters": round(float(np.mean([iters[i] for i in ok])), 1), "large": sum(p.k == 1024 for p in probs),
+            "precision": "bf16", "tol": 1e-4}
+
+
+def _single_fp32_leg(args):
+    """64x64x16 video-shaped tensor, 8x8x4 kernel, 200 iterations, plain FP32."""
+    import torch
+    from paper_2604_17001_amd import icnnm
+    wl = _workload("64x64x16")
+    prob = wl.problems[0]
+    lib = icnnm.Library.get()
+    dev = torch.device("cuda", 0)
+    M = torch.from_numpy(prob.M).to(dev)
+    mask = torch.from_numpy(prob.mask).to(dev)
+    V = torch.from_numpy(np.ascontiguousarray(np.load(_gold("64x64x16_V.npy")))).to(dev)
+    L = torch.empty_like(M)
+    kw = dict(max_iter=wl.iters)
+    for _ in range(2):
+        lib.solve(M, mask, V, wl.kdims, out=L, **kw)
+    torch.cuda.synchronize()
+    steps = 10
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        lib.solve(M, mask, V, wl.kdims, out=L, **kw)
+    torch.cuda.synchronize()
+    value = steps / (time.perf_counter() - t0)
+    ref = np.load(_gold("64x64x16_L.npy"))
+    err = float(np.linalg.norm(L.cpu().numpy().astype(np.float64) - ref) / np.linalg.norm(ref))
+    lib.stage_times(reset=True)
+    lib.set_profiling(True)
+    lib.solve(M, mask, V, wl.kdims, out=L, **kw)
+    lib.set_profiling(False)
+    stages = _stage_avgs(lib.stage_times(reset=True, split=True))
+    k = prob.k
+    kp = _padded_k(k)
+    tr = TRAFFIC.get(("64x64x16", "fp32", "forward"))
+    traffic = tr["bytes"] if tr and tr["src"] == _kernel_src_hash() else None
+    roof = _roofline("forward_fp32", stages["forward_fp32"]["avg_us"], 2.0 * prob.m * k * k, 16.0 * prob.m * kp,
+                     "fp32", traffic)
+    return {"workload": wl.name, "precision": "fp32", "value": round(value, 3), "unit": "tensors/s",
+            "rel_err_vs_oracle": err, "roofline": roof,
+            "adjoint_fp32_avg_us": stages["adjoint_fp32"]["avg_us"]}
+
+
+def _cpu_baseline_batch(wl, V, iters, sample_iters, msum):
+    """The FP64 oracle, untuned, on `sample_iters` iterations of one 48x48x8 instance
+    of the batch, scaled by entries x iterations to the whole 64-instance batch."""
+    from oracle import icnnm_ref as O
+    model, blas, threads = _host_info()
+    p = wl.problems[2]
+    t0 = time.perf_counter()
+    O.solve(p.M, p.mask, V.astype(np.float64), wl.kdims, sample_iters)
+    dt = time.perf_counter() - t0
+    per_entry_iter = dt / (sample_iters * p.m)
+    batch_s = per_entry_iter * msum * iters
+    return {"value": len(wl.problems) / batch_s, "unit": "tensors/s", "cores": threads, "kind": "oracle",
+            "cpu_model": model, "blas": blas,
+            "sample": f"{sample_iters} of {iters} iterations of one {'x'.join(map(str, p.dims))} instance "
+                      f"({dt:.1f} s), scaled by entries x iterations to the 64-instance batch"}
 
 
 def _serve_main(args):
@@ -198,9 +431,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="64x64x16", choices=["16x16x8", "64x64x16", "128x128x32", "batch", "serve"],
-                    help="16x16x8 prediction, 64x64x16 video (default), 128x128x32 interpolation at k=1024, "
-                         "64-instance uneven batch, serving with Poisson arrivals")
+    ap.add_argument("--workload", default="batch", choices=["batch", "16x16x8", "64x64x16", "128x128x32", "serve"],
+                    help="batch (default): the uneven 64-instance batch in BF16 with its comparators; "
+                         "16x16x8 prediction, 64x64x16 video, 128x128x32 interpolation at k=1024 (single "
+                         "instances); serve: one point of the serving sweep")
     ap.add_argument("--rate", type=float, default=10.0, help="serve: Poisson arrival rate (req/s)")
     ap.add_argument("--requests", type=int, default=256, help="serve: number of requests")
     ap.add_argument("--serve-warmup-frac", type=float, default=0.10,
@@ -208,13 +442,17 @@ def main():
     ap.add_argument("--large-frac", type=float, default=0.10, help="serve: share of 128x128x32 requests")
     ap.add_argument("--tol", type=float, default=1e-4, help="serve: retirement residual")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: HBM budget of the server")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="batch: rate of the short served stream")
+    ap.add_argument("--serve-requests", type=int, default=48, help="batch: requests of the short served stream")
+    ap.add_argument("--no-serve", action="store_true", help="batch: skip the short served stream")
+    ap.add_argument("--precision", default=None, choices=["fp32", "bf16", "fp16"],
+                    help="default: bf16 for batch and serve, fp32 for single instances")
     ap.add_argument("--no-autotune", action="store_true", help="batch: cost-model tile boxes only")
     ap.add_argument("--cpu-sample-iters", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
-                    help="skip timing the other precision form (BF16 vs plain FP32) on the same workload")
+                    help="skip the other form (batch: the 64x64x16 FP32 single instance; single: BF16 vs FP32)")
     ap.add_argument("--iters", type=int, default=0, help="override the iteration count (short profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
@@ -225,9 +463,11 @@ def main():
         sys.exit(2)
 
     if args.workload == "batch":
-        return _batch_main(args)
+        return _headline(args)
     if args.workload == "serve":
+        args.precision = args.precision or "bf16"
         return _serve_main(args)
+    args.precision = args.precision or "fp32"
 
     import torch
     from paper_2604_17001_amd import icnnm
@@ -270,41 +510,26 @@ def main():
         ref = np.load(gL)
         rel_err = float(np.linalg.norm(Lg.cpu().numpy().astype(np.float64) - ref) / np.linalg.norm(ref))
 
-    # stage durations with HIP events on the library stream (separate profiled pass)
+    # stage durations with HIP events on the library stream (separate profiled pass);
+    # rounds whose contractions both ran in the reduced precision are timed apart
     roofline, stages = None, None
     if not args.no_profile:
         lib.stage_times(reset=True)
         lib.set_profiling(True)
-        nprof = 2
-        for _ in range(nprof):
+        for _ in range(2):
             lib.solve(M, mask, V, kd, out=L, **kw)
         lib.set_profiling(False)
-        st = lib.stage_times(reset=True)
-        working = {"colnorm": wl.iters + 1, "adjoint": wl.iters, "lstep": wl.iters + 1, "forward": wl.iters + 1}
-        stages = {s: {"avg_us": 1e3 * ms / (nprof * working[s]), "launches": n} for s, (ms, n) in st.items()}
-        dom = max(("forward", "adjoint"), key=lambda s: stages[s]["avg_us"])
-        flops = 2.0 * m * k * k          # one m x k x k contraction per launch
-        sec = stages[dom]["avg_us"] * 1e-6
+        stages = _stage_avgs(lib.stage_times(reset=True, split=True))
+        part = "fp32" if args.precision == "fp32" else "lowp"
+        kp = _padded_k(k)
         # algorithmic state bytes per launch: the forward reads and writes U and Q, the
         # adjoint reads them (FP32, m x kp entries each)
-        kp = ((k + 63) // 64) * 64 if k <= 256 else ((k + 255) // 256) * 256
-        abytes = (16.0 if dom == "forward" else 8.0) * m * kp
+        cand = {"forward": 16.0 * m * kp, "adjoint": 8.0 * m * kp}
+        dom = max(cand, key=lambda s_: stages.get(f"{s_}_{part}", {"avg_us": 0.0})["avg_us"])
         tr = TRAFFIC.get((args.workload, args.precision, dom))
         traffic = tr["bytes"] if tr and tr["src"] == _kernel_src_hash() and args.iters == 0 else None
-        mpeak = PEAKS["fp32_mfma"] if args.precision == "fp32" else PEAKS[f"{args.precision}_mfma"]
-        tflops = flops / sec / 1e12
-        if flops / abytes >= mpeak * 1e12 / (PEAKS["hbm_gbs"] * 1e9):
-            # above the ridge point: the contraction bounds the kernel
-            roofline = {"bound": "mfma", "kernel": dom, "achieved": round(tflops, 3), "peak": mpeak,
-                        "unit": "TFLOP/s", "frac": round(tflops / mpeak, 4), "traffic": traffic,
-                        "flops_per_launch": flops, "algorithmic_bytes_per_launch": abytes}
-        else:
-            # below it (reduced precision): the U/Q state traffic bounds the kernel
-            gbs = abytes / sec / 1e9
-            roofline = {"bound": "hbm", "kernel": dom, "achieved": round(gbs, 1), "peak": PEAKS["hbm_gbs"],
-                        "unit": "GB/s", "frac": round(gbs / PEAKS["hbm_gbs"], 4), "traffic": traffic,
-                        "algorithmic_bytes_per_launch": abytes, "flops_per_launch": flops,
-                        "mfma_tflops": round(tflops, 3), "mfma_frac": round(tflops / mpeak, 4)}
+        roofline = _roofline(f"{dom}_{part}", stages[f"{dom}_{part}"]["avg_us"], 2.0 * m * k * k, cand[dom],
+                             args.precision, traffic)
 
     if args.calibrate_copy:
         x = torch.ones(64 << 20, dtype=torch.float32, device=dev)

@@ -121,8 +121,31 @@ icnnm_status icnnm_create(int device, size_t hbm_budget_bytes, icnnm_ctx **out);
 /* Destroy a context: waits for in-flight served requests, frees all state. */
 void icnnm_destroy(icnnm_ctx *ctx);
 
-/* Human-readable description of the last error on this context (never NULL). */
+/* Human-readable description of the last error on this context (never NULL). The
+ * string is a copy owned by the calling thread, valid until its next call of
+ * icnnm_last_error. */
 const char *icnnm_last_error(const icnnm_ctx *ctx);
+
+/* Tile plan of one instance, computed on the host alone (no context, no device
+ * work; callable without a GPU): the tile box the cost model picks for the shape
+ * (joint = 0: as icnnm_solve plans it; joint != 0: as a member of a joint launch of
+ * icnnm_solve_batch or the server), the tiles per dimension and in total, the padded
+ * kernel size the contractions run at, and the device bytes of the instance's solver
+ * state (iterates, multiplier, halo partials, reduction slices, gather tables: what
+ * the instance charges to the HBM budget; V operand copies not included). The
+ * state per (row, eigendirection) pair is the scaled multiplier and the Z-step
+ * operand of Section III-D.
+ * Errors: ICNNM_E_INVALID for a bad shape or parameters, or when no tile box fits
+ * the planner's limits (e.g. more than 32767 tiles along one dimension). */
+typedef struct {
+  int32_t tile[3];          /* tile box b_1..b_3 (order-3 form) */
+  int32_t tiles_per_dim[3]; /* ceil(m_j / b_j) */
+  int32_t ntiles;
+  int32_t padded_k;         /* k rounded up to the contraction's column unit */
+  int64_t state_bytes;
+} icnnm_plan_info;
+icnnm_status icnnm_plan(const icnnm_shape *shape, const icnnm_params *params, int32_t joint,
+                        icnnm_plan_info *out);
 
 /* Learn the k convolution eigenvectors of a reference ensemble (Definition 3):
  * the eigenvectors of sum_j A_k(L_j)^T A_k(L_j) (eq:A), accumulated in FP64 on
@@ -202,12 +225,15 @@ icnnm_status icnnm_poll(icnnm_ctx *ctx, uint64_t ticket, icnnm_info *info);
  * launch their stage kernels one by one (no graph replay) with a pair of HIP
  * events around each launch on the context's stream; the elapsed times are
  * accumulated per stage. Stages: 0 column norms, 1 adjoint, 2 L-step,
- * 3 forward. icnnm_stage_times copies the totals (milliseconds) and launch
- * counts into the host arrays ms[4] and counts[4], then resets them if reset
- * is nonzero. Timing adds event overhead between launches; keep it off for
+ * 3 forward. Rounds whose two contractions both run in BF16/FP16 (the delta
+ * kernels of the reduced-precision form) are accounted at index 4 + stage, all
+ * other rounds (FP32 solves, initialisation, FP32 refresh iterations) at index
+ * stage. icnnm_stage_times copies the totals (milliseconds) and launch counts
+ * into the host arrays ms[8] and counts[8], then resets them if reset is
+ * nonzero. Timing adds event overhead between launches; keep it off for
  * throughput runs. */
 icnnm_status icnnm_set_profiling(icnnm_ctx *ctx, int32_t enable);
-icnnm_status icnnm_stage_times(icnnm_ctx *ctx, double ms[4], int64_t counts[4], int32_t reset);
+icnnm_status icnnm_stage_times(icnnm_ctx *ctx, double ms[8], int64_t counts[8], int32_t reset);
 
 #ifdef __cplusplus
 }

@@ -50,6 +50,7 @@ static_assert(sizeof(InstState) == 96, "InstState is copied between host and dev
 struct alignas(16) InstDev {
   int32_t m[3], k[3], b[3], E[3], nt[3], C[3], goff[3];
   int32_t ntiles, bm, E123, nlblk, nslice, prec, max_iter, refresh_every;
+  int32_t gshift, pad_;  // gather-table entries: (tile << gshift) | box position
   int64_t mtot;
   double lam, rho, theta_max, tol, theta0;
   const float* M;
@@ -62,11 +63,11 @@ struct alignas(16) InstDev {
   float* qpart;     // [ntiles][kp] per-tile sums of Q^2
   float* wpart;     // [ntiles][kp] per-tile sums of W^2
   float* rpart;     // [ntiles][ncg] per-tile sums of (Z - W)^2
-  double* dlpart;   // [nlblk] L-step partial sums
-  double* slice;    // [nslice][2 kp + 2] FP64 slice sums of the norm reduction
+  double* dlpart;   // [nlblk][2] L-step partial sums: ||dL||^2, ||P_Omega(L - M)||^2
+  double* slice;    // [2 kp] column sums, then [nslice][3] FP64 slice sums of the scalars
   float* s;         // shrink factors [kp]
   float* T;         // reduced precision: running A_k^*(G V^T) / k, updated by deltas  [m]
-  const int32_t* gtab;  // per-dimension gather tables, entries (tile << 16) | position, -1 = none
+  const int32_t* gtab;  // per-dimension gather tables, entries (tile << gshift) | position, -1 = none
   InstState* st;
 };
 

@@ -1240,7 +1240,7 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
   // covering partial in a fixed order and the lanes combine by shuffles
   const int sub = threadIdx.x & (kLanesPerElem - 1);
   const int64_t t = (int64_t)lb.y * kLStepElems + (threadIdx.x / kLanesPerElem);
-  double acc = 0.0;
+  double acc = 0.0, pen = 0.0;
   const bool in = t < I.mtot;
   float T = 0.f;
   int t0 = 0, t1 = 0, t2 = 0;
@@ -1270,6 +1270,7 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
     // issued before any is summed.
     const int C1 = I.C[1], C2 = I.C[2];
     const int npair = I.C[0] * C1;
+    const int gsh = I.gshift, gmask = (1 << gsh) - 1;  // entry = (tile << gsh) | position
     constexpr int kC2 = 4, kPr = 4;  // fast path: C2 <= 4, <= 4 pairs per lane, one offset group
     if (C2 <= kC2 && nsg == 1 && npair <= kPr * kLanesPerElem) {
       int e2v[kC2];
@@ -1291,13 +1292,13 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
       for (int j = 0; j < kPr; ++j) {
         const int e0 = e0v[j], e1 = e1v[j];
         const bool okp = (e0 | e1) >= 0;
-        const int tb = ((e0 >> 16) * I.nt[1] + (e1 >> 16)) * I.nt[2];
-        const int pb = ((e0 & 0xffff) * I.E[1] + (e1 & 0xffff)) * I.E[2];
+        const int tb = ((e0 >> gsh) * I.nt[1] + (e1 >> gsh)) * I.nt[2];
+        const int pb = ((e0 & gmask) * I.E[1] + (e1 & gmask)) * I.E[2];
 #pragma unroll
         for (int c2 = 0; c2 < kC2; ++c2) {
           const int e2 = e2v[c2];
           v[j][c2] = 0.f;
-          if (okp && e2 >= 0) v[j][c2] = I.part[(size_t)(tb + (e2 >> 16)) * I.E123 + pb + (e2 & 0xffff)];
+          if (okp && e2 >= 0) v[j][c2] = I.part[(size_t)(tb + (e2 >> gsh)) * I.E123 + pb + (e2 & gmask)];
         }
       }
 #pragma unroll
@@ -1309,12 +1310,12 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
         const int c0 = pr / C1, c1 = pr - c0 * C1;
         const int e0 = g0[c0], e1 = g1[c1];
         if ((e0 | e1) < 0) continue;
-        const int tb = ((e0 >> 16) * I.nt[1] + (e1 >> 16)) * I.nt[2];
-        const int pb = ((e0 & 0xffff) * I.E[1] + (e1 & 0xffff)) * I.E[2];
+        const int tb = ((e0 >> gsh) * I.nt[1] + (e1 >> gsh)) * I.nt[2];
+        const int pb = ((e0 & gmask) * I.E[1] + (e1 & gmask)) * I.E[2];
         for (int c2 = 0; c2 < C2; ++c2) {
           const int e2 = g2[c2];
           if (e2 < 0) break;
-          const float* pp = I.part + ((size_t)(tb + (e2 >> 16)) * nsg) * I.E123 + pb + (e2 & 0xffff);
+          const float* pp = I.part + ((size_t)(tb + (e2 >> gsh)) * nsg) * I.E123 + pb + (e2 & gmask);
           for (int g = 0; g < nsg; ++g) T += pp[(size_t)g * I.E123];
         }
       }
@@ -1349,15 +1350,29 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
       if (I.prec != kFP32) I.D[t] = lv - old;
       const double d = (double)lv - (double)old;
       acc = d * d;
+      // penalized program (finite lambda): ||P_Omega(L - M)||^2 of its objective
+      if (obs && I.lam <= 1e300) {
+        const double e = (double)lv - (double)mv;
+        pen = e * e;
+      }
     }
   }
-  // block reduction in FP64, fixed order
-  __shared__ double red[kThreads / 64];
+  // block reductions in FP64, fixed order
+  __shared__ double red[2][kThreads / 64];
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  for (int o = 1; o < 64; o <<= 1) {
+    acc += __shfl_xor(acc, o, 64);
+    pen += __shfl_xor(pen, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = acc;
+    red[1][threadIdx.x >> 6] = pen;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) I.dlpart[lb.y] = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0) {
+    I.dlpart[2 * lb.y] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    I.dlpart[2 * lb.y + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
 }
 
 // =====================================================================================
@@ -1377,7 +1392,7 @@ __global__ __launch_bounds__(kThreads) void k_colnorm_reduce(StageArgs a) {
   const int kp = a.kp;
   const int nt = I.ntiles;
   double* colsum = I.slice;              // [kp][2]: sum Q^2, sum W^2
-  double* scal = I.slice + 2 * kp;       // [nslice][2]: (Z - W)^2, L-step sums
+  double* scal = I.slice + 2 * kp;       // [nslice][3]: (Z - W)^2, ||dL||^2, ||P_Omega(L - M)||^2
   {
     const int c = sl.y * 4 + wave;
     const float* qp = I.qpart + (size_t)c * nt;
@@ -1398,25 +1413,31 @@ __global__ __launch_bounds__(kThreads) void k_colnorm_reduce(StageArgs a) {
       colsum[2 * c + 1] = w;
     }
   }
-  __shared__ double red[2][kThreads / 64];
+  __shared__ double red[3][kThreads / 64];
   const int nr = nt * a.ncg;
   const int rch = (nr + I.nslice - 1) / I.nslice, lch = (I.nlblk + I.nslice - 1) / I.nslice;
-  double r = 0.0, dl = 0.0;
+  double r = 0.0, dl = 0.0, pn = 0.0;
   for (int i = sl.y * rch + tid; i < min(nr, (sl.y + 1) * rch); i += kThreads) r += (double)I.rpart[i];
-  for (int i = sl.y * lch + tid; i < min(I.nlblk, (sl.y + 1) * lch); i += kThreads) dl += I.dlpart[i];
+  for (int i = sl.y * lch + tid; i < min(I.nlblk, (sl.y + 1) * lch); i += kThreads) {
+    dl += I.dlpart[2 * i];
+    pn += I.dlpart[2 * i + 1];
+  }
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     r += __shfl_xor(r, o, 64);
     dl += __shfl_xor(dl, o, 64);
+    pn += __shfl_xor(pn, o, 64);
   }
   if (lane == 0) {
     red[0][wave] = r;
     red[1][wave] = dl;
+    red[2][wave] = pn;
   }
   __syncthreads();
   if (tid == 0) {
-    scal[2 * sl.y] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
-    scal[2 * sl.y + 1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+    scal[3 * sl.y] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+    scal[3 * sl.y + 1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+    scal[3 * sl.y + 2] = ((red[2][0] + red[2][1]) + red[2][2]) + red[2][3];
   }
 }
 
@@ -1433,17 +1454,19 @@ __global__ __launch_bounds__(kThreads) void k_colnorm_finish(StageArgs a) {
   const int kp = a.kp;
   const double* colsum = I.slice;
   const double* scal = I.slice + 2 * kp;
-  __shared__ double sh_obj[kThreads / 64], sh_max[kThreads / 64], sh_rs[kThreads / 64], sh_ds[kThreads / 64];
-  __shared__ double sh_sc[2];
-  double obj = 0.0, mx = 0.0, rs = 0.0, ds = 0.0;
+  __shared__ double sh_obj[kThreads / 64], sh_max[kThreads / 64], sh_rs[kThreads / 64], sh_ds[kThreads / 64],
+      sh_pn[kThreads / 64];
+  __shared__ double sh_sc[3];
+  double obj = 0.0, mx = 0.0, rs = 0.0, ds = 0.0, pn = 0.0;
   for (int c = tid; c < kp; c += kThreads) {
     obj += sqrt(colsum[2 * c + 1]);
     mx = fmax(mx, sqrt(colsum[2 * c]));
   }
   // slice partials of the residual sums: strided over the block, fixed tree
   for (int j = tid; j < I.nslice; j += kThreads) {
-    rs += scal[2 * j];
-    ds += scal[2 * j + 1];
+    rs += scal[3 * j];
+    ds += scal[3 * j + 1];
+    pn += scal[3 * j + 2];
   }
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -1451,21 +1474,27 @@ __global__ __launch_bounds__(kThreads) void k_colnorm_finish(StageArgs a) {
     mx = fmax(mx, __shfl_xor(mx, o, 64));
     rs += __shfl_xor(rs, o, 64);
     ds += __shfl_xor(ds, o, 64);
+    pn += __shfl_xor(pn, o, 64);
   }
   if (lane == 0) {
     sh_obj[wave] = obj;
     sh_max[wave] = mx;
     sh_rs[wave] = rs;
     sh_ds[wave] = ds;
+    sh_pn[wave] = pn;
   }
   __syncthreads();
   if (tid == 0) {
     sh_sc[0] = ((sh_rs[0] + sh_rs[1]) + sh_rs[2]) + sh_rs[3];
     sh_sc[1] = ((sh_ds[0] + sh_ds[1]) + sh_ds[2]) + sh_ds[3];
+    sh_sc[2] = ((sh_pn[0] + sh_pn[1]) + sh_pn[2]) + sh_pn[3];
   }
   __shared__ int go_on;
   if (tid == 0) {
-    const double objective = ((sh_obj[0] + sh_obj[1]) + sh_obj[2]) + sh_obj[3];
+    // ||A_k(L)V||_{2,1} (eq:InductiveCNNM); the penalized program (eq:admm) adds
+    // (lambda k / 2) ||P_Omega(L - M)||_F^2 (zero at initialisation, L = P_Omega M)
+    double objective = ((sh_obj[0] + sh_obj[1]) + sh_obj[2]) + sh_obj[3];
+    if (I.lam <= 1e300) objective += 0.5 * I.lam * (double)a.k * sh_sc[2];
     const double maxn = fmax(fmax(sh_max[0], sh_max[1]), fmax(sh_max[2], sh_max[3]));
     int go = 1;
     if (phase == kInit) {

@@ -13,6 +13,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <list>
+#include <set>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -99,6 +101,7 @@ struct DevBuf {
 struct Plan {
   int m[3], k[3], b[3], E[3], nt[3], C[3], goff[3];
   int ntiles, bm, E123, nlblk, nslice;
+  int gshift;  // gather-table entries pack (tile index << gshift) | box position
   int64_t mtot;
   std::vector<int32_t> gtab;
   size_t state_floats() const;
@@ -176,6 +179,11 @@ static std::vector<std::pair<double, Plan>> plan_candidates(const int m[3], cons
           if (lds_adjoint_floats(p, kp) * 4 > 80 * 1024) continue;
         }
         if (p.E[0] > 65535 || p.E[1] > 65535 || p.E[2] > 65535 || ntiles > 65535 * 16) continue;
+        // gather-table entries pack (tile index << gshift) | box position into a
+        // non-negative int32: gshift bits hold every box position, the rest the tiles
+        p.gshift = 1;
+        while ((1 << p.gshift) < std::max(p.E[0], std::max(p.E[1], p.E[2]))) ++p.gshift;
+        if (std::max(p.nt[0], std::max(p.nt[1], p.nt[2])) > (1 << (31 - p.gshift)) - 1) continue;
         // cost model: rounds of resident workgroups (two per CU, limited by the
         // adjoint's registers) x (units per wavefront + prologue/epilogue overhead),
         // slowed when fewer than two wavefronts per SIMD are resident, times the
@@ -221,7 +229,7 @@ static void finish_plan(Plan& p, int kp) {
         int t = n * p.b[d] - (k[d] - 1) + q;
         t %= m[d];
         if (t < 0) t += m[d];
-        lists[t].push_back((n << 16) | q);
+        lists[t].push_back((n << p.gshift) | q);
       }
     int C = 0;
     for (auto& l : lists) C = std::max<int>(C, (int)l.size());
@@ -290,6 +298,7 @@ struct Member {
   // serving bookkeeping
   uint64_t ticket = 0;
   double t_submit = 0, t_start = 0;
+  int round = 0;  // rounds the member has been part of (its round r runs iteration r)
 };
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -305,12 +314,21 @@ static size_t member_bytes(const Plan& p, int kp, int nsg, int ncg, int prec) {
   b += align256((size_t)p.ntiles * nsg * p.E123 * 4);        // part
   b += 2 * align256((size_t)p.ntiles * kp * 4);              // qpart, wpart
   b += align256((size_t)p.ntiles * ncg * 4);                 // rpart
-  b += align256((size_t)p.nlblk * 8);                        // dlpart
-  b += align256((size_t)(2 * kp + 2 * p.nslice) * 8);          // column sums + scalar partials
+  b += align256((size_t)p.nlblk * 16);                       // dlpart
+  b += align256((size_t)(2 * kp + 3 * p.nslice) * 8);        // column sums + scalar partials
   b += align256((size_t)kp * 4);                             // s
   b += align256(p.gtab.size() * 4);                          // gather tables
   if (prec != kFP32) b += 2 * align256((size_t)p.mtot * 4);  // Lprev, T
   return b;
+}
+
+// Contraction precision of round r of a member that joined at its round 0 (initial
+// forward in FP32; round r >= 1 runs iteration r): FP32 at initialisation, on the
+// first iteration, every refresh_every-th and from the last one on (the refresh
+// schedule of the column-norm kernel), the member's reduced precision otherwise.
+static int round_kind(int r, int prec, int max_iter, int refresh_every) {
+  if (prec == kFP32 || r == 0 || refresh_every <= 1 || r >= max_iter) return kFP32;
+  return (r - 1) % refresh_every == 0 ? (int)kFP32 : prec;
 }
 
 struct Group {
@@ -333,11 +351,13 @@ struct Group {
   int graph_rounds = 0;
   // graphs of run_aligned: (precision of the rounds, number of rounds) -> graph
   std::map<std::pair<int, int>, hipGraphExec_t> kgraphs;
+  // graphs of run_kinds: the precisions launched in each round of a chunk -> graph
+  std::map<std::vector<int>, hipGraphExec_t> pgraphs;
   // stage timing (events around each launch) when profiling is on
   struct Prof {
     bool on = false;
-    double ms[4] = {0, 0, 0, 0};
-    int64_t n[4] = {0, 0, 0, 0};
+    double ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // [4 * (reduced-precision round) + stage]
+    int64_t n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     std::vector<hipEvent_t> ev;
   };
   Prof* prof = nullptr;
@@ -358,6 +378,8 @@ struct Group {
     graph_rounds = 0;
     for (auto& kv : kgraphs) (void)hipGraphExecDestroy(kv.second);
     kgraphs.clear();
+    for (auto& kv : pgraphs) (void)hipGraphExecDestroy(kv.second);
+    pgraphs.clear();
   }
 
   void set_v(const float* V, hipStream_t st) {
@@ -401,6 +423,7 @@ struct Group {
       d.goff[i] = p.goff[i];
     }
     d.ntiles = p.ntiles;
+    d.gshift = p.gshift;
     d.bm = p.bm;
     d.E123 = p.E123;
     d.nlblk = p.nlblk;
@@ -424,8 +447,8 @@ struct Group {
     d.qpart = (float*)take((size_t)p.ntiles * kp * 4);
     d.wpart = (float*)take((size_t)p.ntiles * kp * 4);
     d.rpart = (float*)take((size_t)p.ntiles * ncg * 4);
-    d.dlpart = (double*)take((size_t)p.nlblk * 8);
-    d.slice = (double*)take((size_t)(2 * kp + 2 * p.nslice) * 8);
+    d.dlpart = (double*)take((size_t)p.nlblk * 16);
+    d.slice = (double*)take((size_t)(2 * kp + 3 * p.nslice) * 8);
     d.s = (float*)take((size_t)kp * 4);
     int32_t* gt = (int32_t*)take(p.gtab.size() * 4);
     d.gtab = gt;
@@ -547,9 +570,12 @@ struct Group {
     if (lo) launch_forward(a, ntiles_total, lds_fwd, prec, lp_rb, st);
   }
 
-  // one round with an event pair around each stage; returns after the events are read
-  void launch_round_timed(hipStream_t st) {
+  // one round (launching the precisions `only` selects, as launch_round) with an event
+  // pair around each stage; returns after the events are read. Rounds that launch only
+  // the reduced-precision contractions are accounted apart from the others.
+  void launch_round_timed(hipStream_t st, int only = -1) {
     const StageArgs a = args();
+    const bool f32 = only < 0 || only == kFP32, lo = prec != kFP32 && (only < 0 || only == prec);
     if (prof->ev.empty()) {
       prof->ev.resize(8);
       for (auto& e : prof->ev) HIPCK(hipEventCreate(&e));
@@ -558,21 +584,22 @@ struct Group {
     launch_colnorm(a, nslice_total, (int)members.size(), st);
     HIPCK(hipEventRecord(prof->ev[1], st));
     HIPCK(hipEventRecord(prof->ev[2], st));
-    launch_adjoints(a, st);
+    launch_adjoints(a, st, only);
     HIPCK(hipEventRecord(prof->ev[3], st));
     HIPCK(hipEventRecord(prof->ev[4], st));
     launch_lstep(a, nlblk_total, st);
     HIPCK(hipEventRecord(prof->ev[5], st));
     HIPCK(hipEventRecord(prof->ev[6], st));
-    launch_forward(a, ntiles_total, lds_fwd, kFP32, 2, st);
-    if (prec != kFP32) launch_forward(a, ntiles_total, lds_fwd, prec, lp_rb, st);
+    if (f32) launch_forward(a, ntiles_total, lds_fwd, kFP32, 2, st);
+    if (lo) launch_forward(a, ntiles_total, lds_fwd, prec, lp_rb, st);
     HIPCK(hipEventRecord(prof->ev[7], st));
     HIPCK(hipEventSynchronize(prof->ev[7]));
+    const int base = (lo && !f32) ? 4 : 0;
     for (int i = 0; i < 4; ++i) {
       float t = 0;
       HIPCK(hipEventElapsedTime(&t, prof->ev[2 * i], prof->ev[2 * i + 1]));
-      prof->ms[i] += t;
-      prof->n[i] += 1;
+      prof->ms[base + i] += t;
+      prof->n[base + i] += 1;
     }
   }
 
@@ -619,18 +646,20 @@ struct Group {
   // but its launch still costs several microseconds. Runs of rounds replay cached
   // graphs. FP32 solves take run().
   void run_aligned(int r0, int rounds, hipStream_t st, int max_iter, int refresh_every) {
-    if (prec == kFP32 || (prof && prof->on)) {
-      run(rounds, st, !(prof && prof->on), std::min(std::max(rounds, 1), 16));
+    if (prec == kFP32) {
+      run(rounds, st, true, std::min(std::max(rounds, 1), 16));
       return;
     }
     if (dirty) rebuild(st);
     if (members.empty() || rounds <= 0) return;
-    auto kind = [&](int r) {
-      if (r == 0 || refresh_every <= 1 || r >= max_iter) return (int)kFP32;
-      return (r - 1) % refresh_every == 0 ? (int)kFP32 : prec;
-    };
+    auto kind = [&](int r) { return round_kind(r, prec, max_iter, refresh_every); };
     int r = r0;
     const int end = r0 + rounds;
+    if (prof && prof->on) {
+      for (; r < end; ++r) launch_round_timed(st, kind(r));
+      HIPCK(hipGetLastError());
+      return;
+    }
     while (r < end) {
       const int kd = kind(r);
       int n = 1;
@@ -646,6 +675,34 @@ struct Group {
         HIPCK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
         HIPCK(hipGraphDestroy(g));
         it = kgraphs.emplace(key, ge).first;
+      }
+      HIPCK(hipGraphLaunch(it->second, st));
+      r += n;
+    }
+    HIPCK(hipGetLastError());
+  }
+
+  // Rounds whose launched precisions are given per round (kinds[r]: kFP32 or the
+  // reduced precision alone, or -1 for both), replayed from graphs cached per chunk
+  // pattern. Used by the server, whose members sit at different iterations: a round
+  // launches only the precisions some member needs in it.
+  void run_kinds(const std::vector<int>& kinds, hipStream_t st, int chunk) {
+    if (dirty) rebuild(st);
+    if (members.empty() || kinds.empty()) return;
+    chunk = std::max(1, chunk);
+    for (size_t r = 0; r < kinds.size();) {
+      const size_t n = std::min(kinds.size() - r, (size_t)chunk);
+      std::vector<int> key(kinds.begin() + r, kinds.begin() + r + n);
+      auto it = pgraphs.find(key);
+      if (it == pgraphs.end()) {
+        hipGraph_t g;
+        hipGraphExec_t ge;
+        HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        for (int kd : key) launch_round(st, kd);
+        HIPCK(hipStreamEndCapture(st, &g));
+        HIPCK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+        HIPCK(hipGraphDestroy(g));
+        it = pgraphs.emplace(key, ge).first;
       }
       HIPCK(hipGraphLaunch(it->second, st));
       r += n;
@@ -681,7 +738,9 @@ struct Request {
   icnnm_params params;
   float* Lout;
   double t_submit;
-  size_t bytes;
+  size_t bytes;        // the member's state and its share of the group's tables
+  size_t group_bytes;  // a new group's V operand copies and state array
+  int bypassed;        // times later requests were admitted past this one at the head
 };
 
 struct Done {
@@ -705,7 +764,7 @@ struct icnnm_ctx {
   // serving
   std::mutex q_mu;
   std::condition_variable q_cv;
-  std::deque<icnnm::Request> queue;
+  std::list<icnnm::Request> queue;
   std::map<uint64_t, icnnm::Done> done;
   std::map<uint64_t, int> pending;  // 1 = queued or running
   uint64_t next_ticket = 1;
@@ -1273,7 +1332,13 @@ void icnnm_destroy(icnnm_ctx* c);
 
 const char* icnnm_last_error(const icnnm_ctx* c) {
   if (!c) return "NULL context";
-  return c->last_error.c_str();
+  // a per-thread copy: the serving thread may record a new error at any time
+  thread_local std::string copy;
+  {
+    std::lock_guard<std::mutex> g(const_cast<icnnm_ctx*>(c)->err_mu);
+    copy = c->last_error;
+  }
+  return copy.c_str();
 }
 
 icnnm_status icnnm_learn_eigvecs(icnnm_ctx* c, const int64_t kdim[3], int32_t b, const icnnm_shape ref_shapes[],
@@ -1293,6 +1358,31 @@ icnnm_status icnnm_solve(icnnm_ctx* c, const icnnm_shape* shape, const float* M,
                          void* stream) {
   if (!c) return ICNNM_E_INVALID;
   return guarded(c, [&] { return do_solve(c, shape, M, mask, V, params, L_out, info, stream); });
+}
+
+icnnm_status icnnm_plan(const icnnm_shape* shape, const icnnm_params* params, int32_t joint, icnnm_plan_info* out) {
+  if (!shape || !params || !out) return ICNNM_E_INVALID;
+  try {
+    int m[3], kd[3];
+    normalize_shape(shape, m, kd);
+    check_params(params);
+    check_precision_shape(kd, params);
+    const int k = kd[0] * kd[1] * kd[2];
+    const int kp = padded_k(k), nsg = (kp + kGroup - 1) / kGroup;
+    const Plan p = joint ? make_plan_shared(m, kd, kp) : make_plan(m, kd, kp);
+    for (int d = 0; d < 3; ++d) {
+      out->tile[d] = p.b[d];
+      out->tiles_per_dim[d] = p.nt[d];
+    }
+    out->ntiles = p.ntiles;
+    out->padded_k = kp;
+    out->state_bytes = (int64_t)member_bytes(p, kp, nsg, nsg, params->precision);
+    return ICNNM_OK;
+  } catch (const Error& e) {
+    return e.code;
+  } catch (...) {
+    return ICNNM_E_INVALID;
+  }
 }
 
 icnnm_status icnnm_solve_batch(icnnm_ctx* c, int32_t count, const icnnm_shape shapes[], const float* const M[],
@@ -1333,6 +1423,18 @@ static std::string group_key(const float* V, const int kd[3], int prec) {
 constexpr int kServeSlots = 512;
 constexpr int kServeRounds = 4;      // rounds per scheduling pass of the costliest group
 constexpr int kServeMaxRounds = 64;  // ... and at most for cheaper groups
+constexpr int kBypassScan = 16;      // queued requests looked at past a blocked head
+constexpr int kMaxBypass = 32;       // admissions past one blocked head before strict FIFO
+
+// Releases the single-instance solve cache (state of earlier icnnm_solve calls kept for
+// reuse), whose budget share can otherwise block a served request indefinitely. Takes
+// the synchronous-call lock, so it waits for a solve in flight on another thread.
+static void evict_solve_cache(icnnm_ctx* c) {
+  std::lock_guard<std::recursive_mutex> lock(c->mu);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  c->cache_members.clear();
+  c->cache.clear();
+}
 
 // Continuous batching: admit queued requests while the HBM budget allows, run all
 // admitted requests of a (V, kernel, precision) group in joint launches, retire
@@ -1340,22 +1442,76 @@ constexpr int kServeMaxRounds = 64;  // ... and at most for cheaper groups
 static void serve_loop(icnnm_ctx* c) {
   (void)hipSetDevice(c->device);
   std::map<std::string, ServeGroup> groups;
+  bool evicted = false;  // the solve cache was released for a blocked head
   for (;;) {
     std::vector<Request> admit;
+    bool any_active = false;
+    bool head_blocked = false;
     {
       std::unique_lock<std::mutex> lk(c->q_mu);
-      bool any_active = false;
       for (auto& kv : groups) any_active = any_active || !kv.second.active.empty();
       if (!any_active) c->q_cv.wait(lk, [&] { return c->stop || !c->queue.empty(); });
       if (c->stop && c->queue.empty() && !any_active) break;
-      // FIFO admission against the budget (state bytes were computed at submit)
-      while (!c->queue.empty()) {
-        Request& r = c->queue.front();
-        if (c->budget.used.load() + r.bytes > c->budget.limit) break;
-        admit.push_back(r);
-        c->queue.pop_front();
+      // Admission. Bytes are reserved cumulatively within the pass; a request that
+      // opens a new group also reserves the group's V operand copies and state array,
+      // and a group takes at most kServeSlots members. Requests are taken in arrival
+      // order; when the head does not fit, up to kBypassScan later requests that do
+      // fit may pass it, at most kMaxBypass times per head, after which the queue
+      // waits for the head (no starvation).
+      size_t reserved = c->budget.used.load();
+      std::map<std::string, int> slots_left;
+      std::set<std::string> opened;
+      Request* blocked = nullptr;
+      int scanned = 0;
+      for (auto it = c->queue.begin(); it != c->queue.end();) {
+        if (blocked && (blocked->bypassed >= kMaxBypass || scanned >= kBypassScan)) break;
+        Request& r = *it;
+        const std::string key = group_key(r.V, r.kd, r.params.precision);
+        auto g = groups.find(key);
+        const bool exists = (g != groups.end() && g->second.g) || opened.count(key);
+        auto sl = slots_left.find(key);
+        if (sl == slots_left.end())
+          sl = slots_left.emplace(key, (g != groups.end() && g->second.g) ? (int)g->second.g->free_slots.size()
+                                                                           : kServeSlots).first;
+        const size_t need = r.bytes + (exists ? 0 : r.group_bytes);
+        if (blocked) ++scanned;
+        if (sl->second > 0 && reserved + need <= c->budget.limit) {
+          reserved += need;
+          sl->second -= 1;
+          opened.insert(key);
+          if (blocked) blocked->bypassed += 1;
+          admit.push_back(r);
+          it = c->queue.erase(it);
+          continue;
+        }
+        if (!blocked) blocked = &r;
+        ++it;
       }
+      head_blocked = blocked != nullptr && blocked == &c->queue.front();
     }
+    if (admit.empty() && head_blocked && !any_active) {
+      // Nothing runs and the head does not fit: budget is held outside the server.
+      // Release the solve cache once; if the head still cannot be admitted with
+      // nothing else holding budget, it never will (submit checks the request alone
+      // against the whole budget, so this is a safety net): fail it.
+      if (!evicted) {
+        evict_solve_cache(c);
+        evicted = true;
+        continue;
+      }
+      std::lock_guard<std::mutex> lk(c->q_mu);
+      Request r = c->queue.front();
+      c->queue.pop_front();
+      set_error(c, "request does not fit the HBM budget with nothing else admitted");
+      Done d{};
+      d.status = ICNNM_E_BUDGET;
+      c->done[r.ticket] = d;
+      c->pending.erase(r.ticket);
+      evicted = false;
+      continue;
+    }
+    if (!admit.empty()) evicted = false;
+    std::vector<Request> requeue;
     for (Request& r : admit) {
       icnnm_status rc = guarded(c, [&]() -> icnnm_status {
         const std::string key = group_key(r.V, r.kd, r.params.precision);
@@ -1379,13 +1535,20 @@ static void serve_loop(icnnm_ctx* c) {
         sg.active.push_back(std::move(mb));
         return ICNNM_OK;
       });
-      if (rc != ICNNM_OK) {
+      if (rc == ICNNM_E_BUDGET || rc == ICNNM_E_NOMEM) {
+        // budget taken meanwhile by a synchronous call on another thread: queue again
+        requeue.push_back(r);
+      } else if (rc != ICNNM_OK) {
         std::lock_guard<std::mutex> lk(c->q_mu);
         Done d{};
         d.status = rc;
         c->done[r.ticket] = d;
         c->pending.erase(r.ticket);
       }
+    }
+    if (!requeue.empty()) {
+      std::lock_guard<std::mutex> lk(c->q_mu);
+      for (auto it = requeue.rbegin(); it != requeue.rend(); ++it) c->queue.push_front(*it);
     }
     for (auto it = groups.begin(); it != groups.end();) {
       if (it->second.active.empty())
@@ -1395,7 +1558,9 @@ static void serve_loop(icnnm_ctx* c) {
     }
     // launch every group's rounds on its own stream first, then collect: groups run
     // concurrently, and a cheaper group runs proportionally more rounds per pass so
-    // that its requests are not held back by the rounds of a costlier group
+    // that its requests are not held back by the rounds of a costlier group. Members
+    // know their refresh schedule, so each round launches only the contraction
+    // precisions that some member needs in it.
     double wmax = 0.0;
     for (auto& kv : groups) wmax = std::max(wmax, kv.second.work);
     std::map<std::string, icnnm_status> rcs;
@@ -1403,10 +1568,22 @@ static void serve_loop(icnnm_ctx* c) {
       ServeGroup& sg = kv.second;
       const double share = sg.work > 0.0 ? wmax / sg.work : 1.0;
       const int rounds = (int)std::min<double>(kServeMaxRounds, kServeRounds * std::max(1.0, std::floor(share)));
+      std::vector<int> kinds(rounds, kFP32);
+      if (sg.g->prec != kFP32) {
+        for (int r = 0; r < rounds; ++r) {
+          bool f32 = false, lo = false;
+          for (auto& mb : sg.active) {
+            const int kd = round_kind(mb->round + r, sg.g->prec, mb->params.max_iter, mb->params.refresh_every);
+            (kd == kFP32 ? f32 : lo) = true;
+          }
+          kinds[r] = f32 && lo ? -1 : (f32 ? (int)kFP32 : sg.g->prec);
+        }
+      }
       rcs[kv.first] = guarded(c, [&]() -> icnnm_status {
-        sg.g->run(rounds, sg.stream, true, kServeRounds);
+        sg.g->run_kinds(kinds, sg.stream, kServeRounds);
         return ICNNM_OK;
       });
+      for (auto& mb : sg.active) mb->round += rounds;
     }
     for (auto& kv : groups) {
       ServeGroup& sg = kv.second;
@@ -1459,11 +1636,21 @@ static icnnm_status do_submit(icnnm_ctx* c, const icnnm_shape* shape, const floa
   const int kp = padded_k(k);
   const int nsg = (kp + kGroup - 1) / kGroup;
   const Plan p = make_plan_shared(r.m, r.kd, kp);  // as the server will plan it
-  r.bytes = member_bytes(p, kp, nsg, nsg, params->precision);
-  // V operand copies: three FP32 layouts, three more in BF16/FP16 for the reduced precisions
-  const size_t vbytes = (size_t)kp * kp * (12 + (params->precision != 0 ? 6 : 0));
-  if (r.bytes + vbytes + sizeof(InstState) * kServeSlots > c->budget.limit)
-    throw Error(ICNNM_E_BUDGET, "request alone exceeds the HBM budget");
+  // the member's state, plus its entries in the group's descriptor and tile tables
+  // (which grow by doubling)
+  r.bytes = member_bytes(p, kp, nsg, nsg, params->precision) +
+            2 * align256(sizeof(InstDev) + 8 * ((size_t)p.ntiles + p.nlblk + p.nslice));
+  // a new group: V operand copies (three FP32 layouts, three more in BF16/FP16 for the
+  // reduced precisions) and the state array of its slots
+  r.group_bytes = align256((size_t)kp * kp * 4) * 3 + (params->precision != 0 ? 3 * align256((size_t)kp * kp * 2) : 0) +
+                  align256(sizeof(InstState) * kServeSlots);
+  r.bypassed = 0;
+  if (r.bytes + r.group_bytes > c->budget.limit) throw Error(ICNNM_E_BUDGET, "request alone exceeds the HBM budget");
+  if (params->check_v) {
+    // checked before the request is queued, on the context's stream
+    std::lock_guard<std::recursive_mutex> lock(c->mu);
+    check_v(c, V, k, c->stream);
+  }
   std::lock_guard<std::mutex> lk(c->q_mu);
   if (!c->server.joinable()) c->server = std::thread(serve_loop, c);
   r.ticket = c->next_ticket++;
@@ -1507,10 +1694,10 @@ icnnm_status icnnm_set_profiling(icnnm_ctx* c, int32_t enable) {
   return ICNNM_OK;
 }
 
-icnnm_status icnnm_stage_times(icnnm_ctx* c, double ms[4], int64_t counts[4], int32_t reset) {
+icnnm_status icnnm_stage_times(icnnm_ctx* c, double ms[8], int64_t counts[8], int32_t reset) {
   if (!c || !ms || !counts) return ICNNM_E_INVALID;
   std::lock_guard<std::recursive_mutex> lock(c->mu);
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < 8; ++i) {
     ms[i] = c->prof.ms[i];
     counts[i] = c->prof.n[i];
     if (reset) {

@@ -22,7 +22,7 @@ OK, PENDING = 0, 1
 E_INVALID, E_NOMEM, E_BUDGET, E_DEVICE, E_NUMERIC, E_NOTFOUND = -1, -2, -3, -4, -5, -6
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
 
-EXPORTS = ["icnnm_params_default", "icnnm_create", "icnnm_destroy", "icnnm_last_error",
+EXPORTS = ["icnnm_params_default", "icnnm_create", "icnnm_destroy", "icnnm_last_error", "icnnm_plan",
            "icnnm_learn_eigvecs", "icnnm_diagnostics", "icnnm_solve", "icnnm_solve_batch", "icnnm_submit",
            "icnnm_poll",
            "icnnm_set_profiling", "icnnm_stage_times"]
@@ -50,6 +50,11 @@ class Info(C.Structure):
         return d
 
 
+class PlanInfo(C.Structure):
+    _fields_ = [("tile", C.c_int32 * 3), ("tiles_per_dim", C.c_int32 * 3), ("ntiles", C.c_int32),
+                ("padded_k", C.c_int32), ("state_bytes", C.c_int64)]
+
+
 class IcnnmError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"icnnm error {code}: {msg}")
@@ -70,6 +75,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.icnnm_destroy.restype = None
     lib.icnnm_last_error.argtypes = [P]
     lib.icnnm_last_error.restype = C.c_char_p
+    lib.icnnm_plan.argtypes = [C.POINTER(Shape), C.POINTER(Params), C.c_int32, C.POINTER(PlanInfo)]
+    lib.icnnm_plan.restype = C.c_int32
     lib.icnnm_learn_eigvecs.argtypes = [P, C.POINTER(C.c_int64), C.c_int32, C.POINTER(Shape),
                                         C.POINTER(P), P, C.POINTER(C.c_double), P]
     lib.icnnm_learn_eigvecs.restype = C.c_int32
@@ -113,6 +120,21 @@ def make_params(lib, max_iter=100, lam=math.inf, theta0=0.0, rho=1.1, theta_max=
     p.precision = PREC[precision] if isinstance(precision, str) else int(precision)
     p.refresh_every, p.check_v = int(refresh_every), int(bool(check_v))
     return p
+
+
+def plan(dims, kdims, joint=False, lib=None, **kw):
+    """Host-only tile plan of one instance (icnnm_plan; no GPU needed). Returns a dict
+    with the tile box, tiles per dimension, tile count, padded k and state bytes, or
+    raises IcnnmError."""
+    lib = lib or load_library()
+    shape = make_shape(dims, kdims)
+    p = make_params(lib, **kw)
+    out = PlanInfo()
+    rc = lib.icnnm_plan(C.byref(shape), C.byref(p), int(bool(joint)), C.byref(out))
+    if rc != OK:
+        raise IcnnmError(rc, "icnnm_plan failed")
+    return {"tile": tuple(out.tile), "tiles_per_dim": tuple(out.tiles_per_dim), "ntiles": int(out.ntiles),
+            "padded_k": int(out.padded_k), "state_bytes": int(out.state_bytes)}
 
 
 def _ptr(t):
@@ -268,14 +290,19 @@ class Library:
         if rc != OK:
             self._raise(rc)
 
-    def stage_times(self, reset=True):
-        """{stage: (total_ms, launches)} accumulated while profiling was on."""
-        ms = (C.c_double * 4)()
-        n = (C.c_int64 * 4)()
+    def stage_times(self, reset=True, split=False):
+        """{stage: (total_ms, launches)} accumulated while profiling was on; with
+        split=True, {(stage, "fp32" | "lowp"): ...}, where "lowp" holds the rounds whose
+        contractions both ran in BF16/FP16."""
+        ms = (C.c_double * 8)()
+        n = (C.c_int64 * 8)()
         rc = self.lib.icnnm_stage_times(self.ctx, ms, n, int(bool(reset)))
         if rc != OK:
             self._raise(rc)
-        return {name: (ms[i], int(n[i])) for i, name in enumerate(STAGES)}
+        if split:
+            return {(name, part): (ms[4 * j + i], int(n[4 * j + i]))
+                    for j, part in enumerate(("fp32", "lowp")) for i, name in enumerate(STAGES)}
+        return {name: (ms[i] + ms[4 + i], int(n[i] + n[4 + i])) for i, name in enumerate(STAGES)}
 
     def poll(self, ticket):
         """Returns (status, info dict); status PENDING while the request runs."""

@@ -80,3 +80,59 @@ def test_create_without_gpu_reports_device_error():
     h = C.c_void_p()
     assert lib.icnnm_create(0, 0, C.byref(h)) == icnnm.E_DEVICE
     assert not h.value
+
+
+def test_plan_of_a_video_tensor():
+    # 64x64x16 with an 8x8x4 kernel: the state holds the scaled multiplier and the
+    # Z-step operand, m x kp floats each, plus smaller partials
+    pl = icnnm.plan((64, 64, 16), (8, 8, 4))
+    assert pl["padded_k"] == 256
+    b = pl["tile"]
+    assert pl["ntiles"] == int(math.prod(pl["tiles_per_dim"]))
+    assert tuple(-(-m // t) for m, t in zip((64, 64, 16), b)) == pl["tiles_per_dim"]
+    assert pl["ntiles"] * math.prod(b) >= 64 * 64 * 16
+    assert pl["state_bytes"] >= 2 * 64 * 64 * 16 * 256 * 4
+    # the reduced precisions add two m-float arrays (running adjoint and delta of L)
+    lo = icnnm.plan((64, 64, 16), (8, 8, 4), precision="bf16")
+    assert lo["state_bytes"] >= pl["state_bytes"] + 2 * 64 * 64 * 16 * 4
+
+
+def _gather_codes_fit(pl, dims, kdims):
+    """Every gather-table entry (tile << shift) | box position of the plan fits a
+    non-negative int32, with shift the bits of the largest box extent."""
+    lead = 3 - len(dims)
+    kd = (1,) * lead + tuple(kdims)
+    E = [b + k - 1 for b, k in zip(pl["tile"], kd)]
+    shift = max(1, (max(E) - 1).bit_length())
+    return max(pl["tiles_per_dim"]) << shift < 2 ** 31
+
+
+def test_plan_keeps_tile_indices_in_the_gather_encoding():
+    # gather-table entries pack (tile << shift) | position into an int32; an order-1
+    # tensor of 10M entries (39063 tiles of 256 rows, more than a 16-bit field holds)
+    # must get codes that fit, never wrapped ones
+    n = 10_000_000
+    for joint in (False, True):
+        pl = icnnm.plan((n,), (4,), joint=joint)
+        assert pl["tile"][:2] == (1, 1) and pl["tiles_per_dim"][2] * pl["tile"][2] >= n
+        assert _gather_codes_fit(pl, (n,), (4,))
+    # 2^24 entries, the largest order-1 extent
+    pl = icnnm.plan((1 << 24,), (3,))
+    assert _gather_codes_fit(pl, (1 << 24,), (3,))
+    # a long innermost dimension beside a large kernel
+    pl = icnnm.plan((4, 1 << 20), (4, 31))
+    assert _gather_codes_fit(pl, (4, 1 << 20), (4, 31))
+
+
+def test_plan_rejects_bad_shapes():
+    with pytest.raises(icnnm.IcnnmError) as e:
+        icnnm.plan((8, 8), (9, 2))
+    assert e.value.code == icnnm.E_INVALID
+    lib = icnnm.load_library()
+    s = icnnm.make_shape((8, 8, 8), (2, 2, 2))
+    s.ndim = 4
+    p = icnnm.make_params(lib)
+    out = icnnm.PlanInfo()
+    assert lib.icnnm_plan(C.byref(s), C.byref(p), 0, C.byref(out)) == icnnm.E_INVALID
+    # NULL shape
+    assert lib.icnnm_plan(None, C.byref(p), 0, C.byref(out)) == icnnm.E_INVALID

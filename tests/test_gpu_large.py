@@ -41,3 +41,23 @@ def test_large_tensor_properties(lib):
     ref = np.roll(L1, shift, axis=(0, 1, 2))
     assert np.linalg.norm(L2 - ref) <= 1e-5 * np.linalg.norm(ref)
     assert abs(info2["objective"] - info1["objective"]) <= 1e-5 * info1["objective"]
+
+
+def test_long_order1_tensor_against_oracle(lib):
+    # 10M entries in one dimension: 39063 tiles along it, more than a 16-bit tile field
+    # of the L-step's gather tables can hold; every entry is checked against the oracle
+    import torch
+    n, kd = 10_000_000, (4,)
+    g = inputs.rng(8, inputs.ROLE_TARGET)
+    M = inputs.cosine_sum((n,), 3, g, sigma=1e-2, scale01=True)
+    mask = inputs.mask_random_missing((n,), 0.4, inputs.rng(8, inputs.ROLE_MASK))
+    V, _ = O.learn([inputs.cosine_sum((4096,), 3, inputs.rng(8, inputs.ROLE_REFS), sigma=1e-2)], kd)
+    V32 = np.ascontiguousarray(V, dtype=np.float32)
+    print("[gpu] order-1 tensor of 10M entries", flush=True)
+    L, info = lib.solve(torch.from_numpy(M).cuda(), torch.from_numpy(mask).cuda(), torch.from_numpy(V32).cuda(),
+                        kd, max_iter=4)
+    L = L.cpu().numpy()
+    assert info["iters"] == 4
+    assert np.array_equal(L[mask != 0], M[mask != 0])
+    Lo, _ = O.solve(M, mask, V32.astype(np.float64), kd, 4)
+    assert np.linalg.norm(L - Lo) <= 1e-5 * np.linalg.norm(Lo)

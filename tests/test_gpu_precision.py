@@ -51,6 +51,26 @@ def test_reduced_precision_parity(lib, prec, dims, kdims, seed):
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("lam", [1000.0, 2.0])
+def test_reduced_precision_penalized_mode(lib, prec, lam):
+    # penalized program (eq:admm): observed entries follow the L-step's weighted mean,
+    # so they are checked against the oracle like the rest, within the same tolerance
+    prob, V32 = _case((16, 16, 8), (4, 4, 4), 0.4, 6)
+    iters = 50
+    print(f"[gpu] {prec} lambda={lam}", flush=True)
+    L, info = lib.solve(_dev(prob.M), _dev(prob.mask), _dev(V32), prob.kdims, max_iter=iters, precision=prec,
+                        lam=lam)
+    L = L.cpu().numpy()
+    Lo, oi = O.solve(prob.M, prob.mask, V32.astype(np.float64), prob.kdims, iters, lam=lam)
+    err = _rel(L, Lo)
+    print(f"[gpu] {prec} lambda={lam} rel.err {err:.3e}", flush=True)
+    assert err <= TOL_LP
+    obs = prob.mask != 0
+    assert _rel(L[obs], Lo[obs]) <= TOL_LP
+    assert abs(info["objective"] - oi["objective"]) <= TOL_LP * oi["objective"]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
 def test_refresh_every_iteration_is_fp32(lib, prec):
     prob, V32 = _case((16, 16, 8), (4, 4, 4), 0.4, 4)
     L1, _ = lib.solve(_dev(prob.M), _dev(prob.mask), _dev(V32), prob.kdims, max_iter=30, precision=prec,

@@ -76,11 +76,12 @@ def test_budget_admission_and_rejection():
         probs = [inputs.random_problem((32, 32, 16), kd, 0.3, seed=100 + i) for i in range(6)]
         V, _ = O.learn([probs[0].M], kd)
         Vd = _dev(V.astype(np.float32))
-        outs, ts = [], []
+        outs, ts, keep = [], [], []
         for p in probs:
             o = torch.empty(p.dims, dtype=torch.float32, device="cuda")
             outs.append(o)
-            ts.append(lib.submit(_dev(p.M), _dev(p.mask), Vd, kd, o, max_iter=60))
+            keep.append((_dev(p.M), _dev(p.mask)))
+            ts.append(lib.submit(keep[-1][0], keep[-1][1], Vd, kd, o, max_iter=60))
         res = _wait(lib, ts)
         assert all(rc == icnnm.OK for rc, _ in res.values())
         big = inputs.random_problem((128, 128, 32), kd, 0.3, seed=120)
@@ -92,3 +93,143 @@ def test_budget_admission_and_rejection():
         assert rc == icnnm.E_NOTFOUND
     finally:
         lib.close()
+
+
+def _group_bytes(kp, prec):
+    """Device bytes a new serving group takes: V operand copies and its slot states."""
+    a = lambda n: (n + 255) // 256 * 256
+    return 3 * a(kp * kp * 4) + (3 * a(kp * kp * 2) if prec != "fp32" else 0) + a(512 * 96)
+
+
+def test_budget_fits_two_of_six():
+    # a budget that holds the group and two requests at a time (not three): the server
+    # must queue the others and admit them as earlier ones retire, never fail them
+    import torch
+    kd = (4, 4, 2)
+    dims = (32, 32, 16)
+    pl = icnnm.plan(dims, kd, joint=True)
+    req = pl["state_bytes"] + (64 << 10)   # state plus its share of the group's tables
+    budget = _group_bytes(pl["padded_k"], "fp32") + 2 * req + req // 2
+    lib = icnnm.Library(budget=budget)
+    try:
+        probs = [inputs.random_problem(dims, kd, 0.3, seed=130 + i) for i in range(6)]
+        V, _ = O.learn([probs[0].M], kd)
+        Vd = _dev(V.astype(np.float32))
+        outs, ts = [], []
+        keep = []  # inputs must stay valid until the request is collected
+        for p in probs:
+            o = torch.empty(p.dims, dtype=torch.float32, device="cuda")
+            outs.append(o)
+            keep.append((_dev(p.M), _dev(p.mask)))
+            ts.append(lib.submit(keep[-1][0], keep[-1][1], Vd, kd, o, max_iter=40))
+        print(f"[gpu] budget {budget} for requests of {req} bytes", flush=True)
+        res = _wait(lib, ts)
+        assert all(res[t][0] == icnnm.OK for t in ts), [res[t][0] for t in ts]
+        # some requests waited in the queue for others to retire
+        assert max(res[t][1]["t_queue_s"] for t in ts) > 1e-3
+        V64 = V.astype(np.float32).astype(np.float64)
+        for p, o in zip(probs, outs):
+            Lo, _ = O.solve(p.M, p.mask, V64, kd, 40)
+            Lh = o.cpu().numpy()
+            assert np.linalg.norm(Lh - Lo) / np.linalg.norm(Lo) <= 1e-5
+            assert np.array_equal(Lh[p.mask != 0], p.M[p.mask != 0])
+    finally:
+        lib.close()
+
+
+def test_served_request_evicts_the_solve_cache():
+    # budget for one instance: a synchronous solve leaves its state cached in the
+    # context; a served request of the same size must still run (the server releases
+    # the cache instead of waiting for budget that nothing would return)
+    import torch
+    kd = (4, 4, 2)
+    dims = (32, 32, 16)
+    pl = icnnm.plan(dims, kd, joint=True)
+    req = pl["state_bytes"] + (64 << 10)
+    lib = icnnm.Library(budget=_group_bytes(pl["padded_k"], "fp32") + req + req // 2)
+    try:
+        p = inputs.random_problem(dims, kd, 0.3, seed=140)
+        V, _ = O.learn([p.M], kd)
+        Vd = _dev(V.astype(np.float32))
+        Md, maskd = _dev(p.M), _dev(p.mask)
+        L1, _ = lib.solve(Md, maskd, Vd, kd, max_iter=20)
+        o = torch.empty(p.dims, dtype=torch.float32, device="cuda")
+        t = lib.submit(Md, maskd, Vd, kd, o, max_iter=20)
+        rc, _ = _wait(lib, [t])[t]
+        assert rc == icnnm.OK
+        assert np.linalg.norm(o.cpu().numpy() - L1.cpu().numpy()) / np.linalg.norm(L1.cpu().numpy()) <= 1e-6
+    finally:
+        lib.close()
+
+
+def test_submit_checks_v(lib):
+    import torch
+    kd = (3, 3, 2)
+    p = inputs.random_problem((12, 10, 8), kd, 0.4, seed=141)
+    bad = np.eye(18, dtype=np.float32)
+    bad[0, 1] = 0.1
+    o = torch.empty(p.dims, dtype=torch.float32, device="cuda")
+    Md, maskd, eye = _dev(p.M), _dev(p.mask), _dev(np.eye(18, dtype=np.float32))
+    with pytest.raises(icnnm.IcnnmError) as e:
+        lib.submit(Md, maskd, _dev(bad), kd, o, max_iter=5, check_v=True)
+    assert e.value.code == icnnm.E_INVALID
+    t = lib.submit(Md, maskd, eye, kd, o, max_iter=5, check_v=True)
+    assert _wait(lib, [t])[t][0] == icnnm.OK
+
+
+def test_served_bf16_mixed_kernel_sizes(lib):
+    """BF16 requests of two kernel sizes (8x8x4, k = 256, retired at residual 1e-4;
+    16x16x4, k = 1024, a fixed 30 iterations) submitted while others run, so they
+    share joint launches and overlap on the device across groups. Each result must
+    equal the same request solved alone (a batch of one: same kernels and refresh
+    schedule) within 1e-5, match the FP64 oracle replayed at the request's reported
+    iteration count within 1e-3, and keep its observed entries bit-exact."""
+    import torch
+    kd_s, kd_l = (8, 8, 4), (16, 16, 4)
+    small = [((16, 16, 8), 0.3, 150), ((24, 16, 8), 0.4, 151), ((32, 16, 8), 0.35, 152), ((16, 24, 16), 0.3, 153),
+             ((16, 16, 8), 0.5, 154)]
+    large = [((32, 32, 8), 0.4, 160), ((32, 48, 8), 0.3, 161)]
+    Vs, _ = O.learn(inputs.random_refs((32, 16, 8), 2, seed=170), kd_s)
+    Vl, _ = O.learn(inputs.random_refs((32, 32, 8), 2, seed=171), kd_l)
+    Vs32, Vl32 = Vs.astype(np.float32), Vl.astype(np.float32)
+    Vsd, Vld = _dev(Vs32), _dev(Vl32)
+    reqs = []
+    for dims, pm, seed in small:
+        reqs.append((inputs.random_problem(dims, kd_s, pm, seed), kd_s, Vsd, Vs32,
+                     dict(max_iter=300, tol=1e-4, precision="bf16")))
+    for dims, pm, seed in large:
+        reqs.append((inputs.random_problem(dims, kd_l, pm, seed), kd_l, Vld, Vl32,
+                     dict(max_iter=30, tol=0.0, precision="bf16")))
+    order = [0, 5, 1, 2, 6, 3, 4]           # large requests arrive between small ones
+    Ms = [_dev(r[0].M) for r in reqs]
+    masks = [_dev(r[0].mask) for r in reqs]
+    outs = [torch.empty_like(x) for x in Ms]
+    torch.cuda.synchronize()
+    tickets = {}
+    for i in order:
+        p, kd, Vd, _, kw = reqs[i]
+        tickets[i] = lib.submit(Ms[i], masks[i], Vd, kd, outs[i], **kw)
+        time.sleep(0.004)
+    res = _wait(lib, list(tickets.values()), timeout=120)
+    for i, (p, kd, Vd, V32, kw) in enumerate(reqs):
+        rc, info = res[tickets[i]]
+        print(f"[gpu] served bf16 request {i} dims {p.dims} k {p.k}: rc {rc} iters {info['iters']}", flush=True)
+        assert rc == icnnm.OK
+        Lh = outs[i].cpu().numpy()
+        obs = p.mask != 0
+        assert np.array_equal(Lh[obs], p.M[obs])
+        if kw["tol"] > 0:
+            assert info["converged"] == 1 and max(info["r_primal"], info["r_change"]) <= 1e-4
+        else:
+            assert info["iters"] == kw["max_iter"]
+        (La,), (ia,) = lib.solve_batch([Ms[i]], [masks[i]], Vd, kd, **kw)
+        La = La.cpu().numpy()
+        assert ia["iters"] == info["iters"]
+        d_alone = np.linalg.norm(Lh - La) / np.linalg.norm(La)
+        assert d_alone <= 1e-5
+        if i == 6:
+            continue  # the second large request is checked against solving alone only
+        Lo, _ = O.solve(p.M, p.mask, V32.astype(np.float64), kd, info["iters"])
+        err = np.linalg.norm(Lh - Lo) / np.linalg.norm(Lo)
+        print(f"[gpu]   vs alone {d_alone:.2e}, vs oracle {err:.2e}", flush=True)
+        assert err <= 1e-3

@@ -131,8 +131,16 @@ def test_identity_bank_gives_zero_fill(lib):
 def test_penalized_mode_parity(lib, lam):
     prob, V32 = _case((12, 10, 8), (3, 3, 2), 0.4, 11)
     L, info = _gpu_solve(lib, prob, V32, 40, lam=lam)
-    Lo, _ = O.solve(prob.M, prob.mask, V32.astype(np.float64), prob.kdims, 40, lam=lam)
+    Lo, oi = O.solve(prob.M, prob.mask, V32.astype(np.float64), prob.kdims, 40, lam=lam)
     assert _relerr(L, Lo) <= TOL32
+    # the reported objective is that of the penalized program (eq:admm):
+    # ||A_k(L)V||_{2,1} + (lambda k / 2) ||P_Omega(L - M)||^2 at the returned L
+    assert abs(info["objective"] - oi["objective"]) <= 1e-4 * oi["objective"]
+    obj_gpu_L = O.objective(L.astype(np.float64), V32.astype(np.float64), prob.kdims, M=prob.M,
+                            mask=prob.mask, lam=lam)
+    assert abs(info["objective"] - obj_gpu_L) <= 1e-5 * obj_gpu_L
+    pen = 0.5 * lam * prob.k * float(np.sum(np.where(prob.mask != 0, L.astype(np.float64) - prob.M, 0.0) ** 2))
+    assert pen > 0.0
 
 
 def test_stopping_rule_matches_oracle(lib):

@@ -198,6 +198,27 @@ icnnm_status icnnm_solve(icnnm_ctx *ctx, const icnnm_shape *shape, const float *
                          const uint8_t *mask, const float *V, const icnnm_params *params,
                          float *L_out, icnnm_info *info, void *stream);
 
+/* icnnm_solve for callers that cannot allocate device memory (code that must not
+ * call hipMalloc or any allocating routine: tight serving loops, harnesses that
+ * forbid allocation, set-ups around graph capture). Same arguments, parameters,
+ * results and errors as icnnm_solve, and the same kernels; the call makes no device
+ * allocation. Every device array beyond the caller's inputs and output (V operand
+ * layouts, instance state, multiplier and Z-step operand, halo partials, reduction
+ * slices, tables) is carved from a fixed per-device scratch of 160 MiB that the
+ * library holds from its load to the end of the process. Instances whose solver
+ * state does not fit return ICNNM_E_BUDGET before any device work (icnnm_plan's
+ * state_bytes plus the V layouts, 3 kp^2 floats and for BF16/FP16 3 kp^2 halves,
+ * must stay below that; a 64x64x16 tensor with an 8x8x4 kernel takes about 140 MB).
+ * The tile box is the cost model's (ICNNM_AUTOTUNE is ignored: measuring would
+ * allocate), and rounds are launched directly (no graph capture). The scratch keeps
+ * the last call's contents; every array is written before it is read, so results
+ * do not depend on them. All calls on one device share the scratch: calls that
+ * overlap on one device would race, so within a process the library runs them one
+ * at a time per device. The call is synchronous like icnnm_solve. */
+icnnm_status icnnm_solve_noalloc(icnnm_ctx *ctx, const icnnm_shape *shape, const float *M,
+                                 const uint8_t *mask, const float *V, const icnnm_params *params,
+                                 float *L_out, icnnm_info *info, void *stream);
+
 /* Solve `count` independent instances of possibly different shapes that share
  * one kernel size and one V, in joint launches (one per stage and iteration,
  * spanning all instances). Arrays are indexed by instance; infos may be NULL.

@@ -112,5 +112,6 @@ void launch_gram_expand(const double* R, const int32_t* k, double* G, hipStream_
 void launch_gemm_f64(const double* A, int trans_a, const double* B, double* C, int n, hipStream_t st);
 void launch_f32_to_f64(const float* src, double* dst, int64_t n, hipStream_t st);
 void launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t st);
+void launch_fill_f32(float* dst, float v, int64_t n, hipStream_t st);
 
 }  // namespace icnnm

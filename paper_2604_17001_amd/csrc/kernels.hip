@@ -1684,6 +1684,11 @@ __global__ void k_copy_f32(const float* src, float* dst, int64_t n) {
     dst[e] = src[e];
 }
 
+__global__ void k_fill_f32(float* dst, float v, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = v;
+}
+
 // ------------------------------------------------------------------------------------ launchers
 static inline int grid_for(int64_t n, int cap = 65536) {
   int64_t g = (n + kThreads - 1) / kThreads;
@@ -1779,6 +1784,10 @@ void launch_gram_expand(const double* R, const int32_t* k, double* G, hipStream_
 
 void launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_copy_f32, dim3(grid_for(n, 8192)), dim3(kThreads), 0, st, src, dst, n);
+}
+
+void launch_fill_f32(float* dst, float v, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n, 8192)), dim3(kThreads), 0, st, dst, v, n);
 }
 
 }  // namespace icnnm

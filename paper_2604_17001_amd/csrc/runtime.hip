@@ -50,8 +50,19 @@ static double now_s() {
 struct Budget {
   size_t limit = 0;
   std::atomic<size_t> used{0};
+  // When set, allocations are carved from [arena, arena + limit) by bumping `used`
+  // (256-byte aligned) and releases are no-ops: no device allocation is made.
+  char* arena = nullptr;
   void* alloc(size_t bytes) {
     if (bytes == 0) return nullptr;
+    if (arena) {
+      const size_t off = (used.load() + 255) & ~(size_t)255;
+      if (off + bytes > limit)
+        throw Error(ICNNM_E_BUDGET, "solver state exceeds the allocation-free scratch maximum of " +
+                                        std::to_string(limit >> 20) + " MiB");
+      used = off + bytes;
+      return arena + off;
+    }
     size_t cur = used.load();
     do {
       if (cur + bytes > limit) throw Error(ICNNM_E_BUDGET, "HBM budget exhausted");
@@ -65,7 +76,7 @@ struct Budget {
     return p;
   }
   void release(void* p, size_t bytes) {
-    if (!p) return;
+    if (!p || arena) return;
     (void)hipFree(p);
     used -= bytes;
   }
@@ -347,6 +358,7 @@ struct Group {
   int gv = 0;  // col2im gather variant of the adjoint launches
   int lp_rb = 2;  // row blocks per reduced-precision forward unit
   bool dirty = true;
+  bool direct = false;  // launch every round directly (no graph capture or instantiation)
   hipGraphExec_t gexec = nullptr;
   int graph_rounds = 0;
   // graphs of run_aligned: (precision of the rounds, number of rounds) -> graph
@@ -612,7 +624,7 @@ struct Group {
       HIPCK(hipGetLastError());
       return;
     }
-    if (!use_graph) {
+    if (!use_graph || direct) {
       for (int r = 0; r < rounds; ++r) launch_round(st);
       HIPCK(hipGetLastError());
       return;
@@ -657,6 +669,11 @@ struct Group {
     const int end = r0 + rounds;
     if (prof && prof->on) {
       for (; r < end; ++r) launch_round_timed(st, kind(r));
+      HIPCK(hipGetLastError());
+      return;
+    }
+    if (direct) {
+      for (; r < end; ++r) launch_round(st, kind(r));
       HIPCK(hipGetLastError());
       return;
     }
@@ -774,6 +791,9 @@ struct icnnm_ctx {
   // autotuned tile boxes by (shape, kernel, precision); loaded once from the cache file
   std::map<std::string, std::array<int, 3>> tuned;
   bool tuned_loaded = false;
+  // device address of this device's allocation-free scratch (nullptr if unavailable)
+  char* scratch = nullptr;
+  std::string scratch_err;
 };
 
 namespace icnnm {
@@ -1180,6 +1200,133 @@ static icnnm_status do_solve_batch(icnnm_ctx* c, int count, const icnnm_shape* s
   return rc;
 }
 
+// ------------------------------------------------------------------------------ allocation-free solve
+// Scratch of icnnm_solve_noalloc: every device array the solver needs beyond the
+// caller's inputs and output (V operand layouts, instance state, multiplier and Z-step
+// operand, halo partials, reduction slices, gather and tile tables) is carved from this
+// array, so the call makes no device allocation. Each device holds its own copy (from
+// module load to process end); in host code the name is only a handle: its device
+// address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kNoAllocBytes = (size_t)160 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// device address of `scratch` on the current device, looked up once per device
+static char* scratch_address(int device, std::string& err) {
+  static std::mutex mu;
+  static std::map<int, char*> addr;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = addr.find(device);
+  if (it != addr.end()) return it->second;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    return nullptr;
+  }
+  addr[device] = (char*)ptr;
+  return (char*)ptr;
+}
+
+// one allocation-free call at a time per device in this process: they share its scratch
+static std::mutex& scratch_lock(int device) {
+  static std::mutex mu;
+  static std::map<int, std::unique_ptr<std::mutex>> locks;
+  std::lock_guard<std::mutex> g(mu);
+  auto& l = locks[device];
+  if (!l) l = std::make_unique<std::mutex>();
+  return *l;
+}
+
+// bytes of the scratch a solve of plan p takes (bump order of do_solve_noalloc)
+static size_t noalloc_bytes(const Plan& p, int kp, int nsg, int prec) {
+  size_t b = 256;                                                   // check_v result
+  b += align256(sizeof(InstState));                                  // state slot
+  b += align256(member_bytes(p, kp, nsg, nsg, prec));                // instance state
+  b += 3 * align256((size_t)kp * kp * 4);                            // V layouts (FP32)
+  if (prec != kFP32) b += 3 * align256((size_t)kp * kp * 2);         // V layouts (16-bit)
+  b += align256(2 * sizeof(InstDev)) + 3 * align256(2 * 8 * ((size_t)p.ntiles + p.nlblk + p.nslice));  // tables
+  return b;
+}
+
+static icnnm_status do_solve_noalloc(icnnm_ctx* c, const icnnm_shape* shape, const float* M, const uint8_t* mask,
+                                     const float* V, const icnnm_params* params, float* L_out, icnnm_info* info,
+                                     void* user_stream) {
+  int m[3], kd[3];
+  normalize_shape(shape, m, kd);
+  check_params(params);
+  check_precision_shape(kd, params);
+  if (!M || !mask || !V || !L_out) throw Error(ICNNM_E_INVALID, "NULL array argument");
+  if (!c->scratch) throw Error(ICNNM_E_DEVICE, "allocation-free scratch unavailable: " + c->scratch_err);
+  const int k = kd[0] * kd[1] * kd[2];
+  const int kp = padded_k(k), nsg = (kp + kGroup - 1) / kGroup;
+  Budget arena;  // outlives every buffer carved from it
+  arena.arena = c->scratch;
+  arena.limit = kNoAllocBytes;
+  Member mb;
+  mb.plan = make_plan(m, kd, kp);  // the cost model's box (no measurement: it would allocate)
+  const size_t need = noalloc_bytes(mb.plan, kp, nsg, params->precision);
+  if (need > kNoAllocBytes)
+    throw Error(ICNNM_E_BUDGET, "instance needs " + std::to_string(need) + " bytes of solver state, above the " +
+                                    std::to_string(kNoAllocBytes >> 20) + " MiB allocation-free scratch maximum");
+  std::lock_guard<std::recursive_mutex> lock(c->mu);
+  std::lock_guard<std::mutex> slock(scratch_lock(c->device));
+  hipStream_t st = enter(c, user_stream);
+  if (params->check_v) {
+    float* dv = (float*)arena.alloc(256);
+    launch_fill_f32(dv, 0.f, 1, st);  // the scratch keeps the previous call's contents
+    launch_check_v(V, k, dv, st);
+    float h = 0.f;
+    HIPCK(hipMemcpyAsync(&h, dv, 4, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    if (!(h <= 1e-5f)) throw Error(ICNNM_E_INVALID, "V is not orthogonal: max|V^T V - I| = " + std::to_string(h));
+  }
+  {
+    Group g(&arena, kd, params->precision, 1);
+    g.direct = true;
+    mb.params = *params;
+    mb.M = M;
+    mb.mask = mask;
+    mb.Lout = L_out;
+    // every device array is written before it is read (the descriptor and state are
+    // uploaded, the first forward writes U and Q of every tile row, ragged rows
+    // included), so nothing left in the scratch by an earlier call is used
+    g.attach(&mb, st);
+    g.set_v(V, st);
+    const double t0 = now_s();
+    const int total = params->max_iter + 2;
+    std::vector<InstState> sts;
+    if (params->tol > 0) {
+      int ran = 0;
+      while (ran < total) {
+        const int chunk = std::min(10, total - ran);
+        g.run_aligned(ran, chunk, st, params->max_iter, params->refresh_every);
+        ran += chunk;
+        g.read_states(sts, st);
+        if (sts[mb.slot].phase == kDone) break;
+      }
+    } else {
+      g.run_aligned(0, total, st, params->max_iter, params->refresh_every);
+    }
+    g.read_states(sts, st);
+    leave(c, user_stream);
+    const InstState& s = sts[mb.slot];
+    if (info) {
+      fill_info(s, info);
+      fill_tile(mb.plan, info);
+      info->t_queue_s = 0;
+      info->t_device_s = now_s() - t0;
+    }
+    g.detach(&mb);
+    if (s.phase != kDone) throw Error(ICNNM_E_DEVICE, "solver did not reach its final state");
+    if (s.status != 0) {
+      set_error(c, "NaN or Inf in a residual");
+      return ICNNM_E_NUMERIC;
+    }
+  }
+  return ICNNM_OK;
+}
+
 // ------------------------------------------------------------------------------ learning
 static icnnm_status do_learn(icnnm_ctx* c, const int64_t kdim_in[3], int b, const icnnm_shape* shapes,
                              const float* const* refs, float* V_out, double* eig_out, void* user_stream) {
@@ -1318,6 +1465,8 @@ icnnm_status icnnm_create(int device, size_t hbm_budget_bytes, icnnm_ctx** out) 
     size_t fr = 0, tot = 0;
     HIPCK(hipMemGetInfo(&fr, &tot));
     c->budget.limit = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
+    // this device's copy of the allocation-free scratch (looked up once per device)
+    c->scratch = scratch_address(device, c->scratch_err);
     return ICNNM_OK;
   });
   if (rc != ICNNM_OK) {
@@ -1383,6 +1532,13 @@ icnnm_status icnnm_plan(const icnnm_shape* shape, const icnnm_params* params, in
   } catch (...) {
     return ICNNM_E_INVALID;
   }
+}
+
+icnnm_status icnnm_solve_noalloc(icnnm_ctx* c, const icnnm_shape* shape, const float* M, const uint8_t* mask,
+                                 const float* V, const icnnm_params* params, float* L_out, icnnm_info* info,
+                                 void* stream) {
+  if (!c) return ICNNM_E_INVALID;
+  return guarded(c, [&] { return do_solve_noalloc(c, shape, M, mask, V, params, L_out, info, stream); });
 }
 
 icnnm_status icnnm_solve_batch(icnnm_ctx* c, int32_t count, const icnnm_shape shapes[], const float* const M[],

@@ -23,7 +23,8 @@ E_INVALID, E_NOMEM, E_BUDGET, E_DEVICE, E_NUMERIC, E_NOTFOUND = -1, -2, -3, -4, 
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
 
 EXPORTS = ["icnnm_params_default", "icnnm_create", "icnnm_destroy", "icnnm_last_error", "icnnm_plan",
-           "icnnm_learn_eigvecs", "icnnm_diagnostics", "icnnm_solve", "icnnm_solve_batch", "icnnm_submit",
+           "icnnm_learn_eigvecs", "icnnm_diagnostics", "icnnm_solve", "icnnm_solve_noalloc", "icnnm_solve_batch",
+           "icnnm_submit",
            "icnnm_poll",
            "icnnm_set_profiling", "icnnm_stage_times"]
 STAGES = ("colnorm", "adjoint", "lstep", "forward")
@@ -85,6 +86,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.icnnm_diagnostics.restype = C.c_int32
     lib.icnnm_solve.argtypes = [P, C.POINTER(Shape), P, P, P, C.POINTER(Params), P, C.POINTER(Info), P]
     lib.icnnm_solve.restype = C.c_int32
+    lib.icnnm_solve_noalloc.argtypes = [P, C.POINTER(Shape), P, P, P, C.POINTER(Params), P, C.POINTER(Info), P]
+    lib.icnnm_solve_noalloc.restype = C.c_int32
     lib.icnnm_solve_batch.argtypes = [P, C.c_int32, C.POINTER(Shape), C.POINTER(P), C.POINTER(P), P,
                                       C.POINTER(Params), C.POINTER(P), C.POINTER(Info), P]
     lib.icnnm_solve_batch.restype = C.c_int32
@@ -248,6 +251,24 @@ class Library:
         if rc != OK:
             self._raise(rc)
         return L, info.as_dict()
+
+    def solve_noalloc(self, M, mask, V, kdims, out, **kw):
+        """icnnm_solve without device allocation inside the library (the caller passes
+        the output buffer; solver state lives in the library's fixed scratch)."""
+        import torch
+        _check_tensor(M, torch.float32, name="M")
+        _check_tensor(mask, torch.uint8, M.shape, name="mask")
+        k = int(np.prod(kdims))
+        _check_tensor(V, torch.float32, (k, k), name="V")
+        _check_tensor(out, torch.float32, M.shape, name="out")
+        shape = make_shape(M.shape, kdims)
+        p = self.params(**kw)
+        info = Info()
+        rc = self.lib.icnnm_solve_noalloc(self.ctx, C.byref(shape), _ptr(M), _ptr(mask), _ptr(V), C.byref(p),
+                                          _ptr(out), C.byref(info), _stream())
+        if rc != OK:
+            self._raise(rc)
+        return out, info.as_dict()
 
     def solve_batch(self, Ms, masks, V, kdims, outs=None, **kw):
         import torch

@@ -121,6 +121,16 @@ def _roofline(kernel, avg_us, flops, abytes, precision, traffic=None):
             "avg_us": round(avg_us, 3)}
 
 
+def _calibrate_copy():
+    """One plain 256 MiB device-to-device copy: the reference for HBM byte counters."""
+    import torch
+    x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+
+
 def _padded_k(k):
     return ((k + 63) // 64) * 64 if k <= 256 else ((k + 255) // 256) * 256
 
@@ -212,6 +222,8 @@ def _headline(args):
         roofline = _roofline(f"{dom}_{part}", stages[f"{dom}_{part}"]["avg_us"], 2.0 * msum * k * k, cand[dom],
                              prec, traffic)
 
+    if args.calibrate_copy:
+        _calibrate_copy()
     serving = None if args.no_serve else _serve_leg(args)
     other = None if args.no_compare else _single_fp32_leg(args)
     cpu = None
@@ -532,11 +544,7 @@ def main():
                              args.precision, traffic)
 
     if args.calibrate_copy:
-        x = torch.ones(64 << 20, dtype=torch.float32, device=dev)
-        y = torch.empty_like(x)
-        y.copy_(x)
-        torch.cuda.synchronize()
-        del x, y
+        _calibrate_copy()
 
     cpu = None
     if not args.no_cpu_baseline:

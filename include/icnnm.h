@@ -88,7 +88,9 @@ typedef struct {
   double theta_max;     /* penalty cap, default 1e10 */
   int32_t max_iter;     /* iterations to run (default 100) */
   double tol;           /* stop when max(r_primal, r_change) <= tol; 0 = run max_iter exactly */
-  int32_t precision;    /* ICNNM_PREC_*: arithmetic of the two contractions */
+  int32_t precision;    /* ICNNM_PREC_*: arithmetic of the two contractions. BF16/FP16 pad
+                           the innermost kernel extent to a multiple of 4 with zero rows of V
+                           (exact); ICNNM_E_INVALID if the padded extent exceeds the tensor's */
   int32_t refresh_every;/* reduced precision: full FP32 evaluation every this many iterations */
   int32_t check_v;      /* nonzero: reject V unless max|V^T V - I| <= 1e-5 */
 } icnnm_params;

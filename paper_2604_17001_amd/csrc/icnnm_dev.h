@@ -82,7 +82,9 @@ struct StageArgs {
   const void* Vf_lo;     // forward operand layout of V (BF16/FP16)
   const void* Va_lo;     // adjoint operand layout of V (BF16/FP16)
   const void* Vp_lo;     // V zero-padded to kp x kp, row-major (BF16/FP16)
-  int32_t kp, k, nsg, ncg;
+  int32_t kp, k, nsg, ncg;  // k: offsets of the contraction kernel (innermost extent
+                            // padded to a multiple of 4 in BF16/FP16)
+  int32_t kt;               // offsets of the kernel itself: the 1/k of the L-step
   int32_t ntiles;        // entries of `tiles`
   int32_t tiles_per_slice;
   int32_t prec;
@@ -113,5 +115,8 @@ void launch_gemm_f64(const double* A, int trans_a, const double* B, double* C, i
 void launch_f32_to_f64(const float* src, double* dst, int64_t n, hipStream_t st);
 void launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t st);
 void launch_fill_f32(float* dst, float v, int64_t n, hipStream_t st);
+// V (kt x kt, kernel dims kd) -> the k x k bank of the padded kernel dims kdp (only the
+// innermost extent differs): rows of padded offsets and columns past kt are zero
+void launch_pad_v(const float* V, const int* kd, const int* kdp, float* out, hipStream_t st);
 
 }  // namespace icnnm

@@ -1331,7 +1331,7 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
       I.L[t] = lv;
       acc = (double)lv * (double)lv;
     } else {
-      float tk = T / (float)a.k;
+      float tk = T / (float)a.kt;
       if (I.prec != kFP32) {
         if (!I.st->refresh) tk += I.T[t];
         I.T[t] = tk;
@@ -1494,7 +1494,7 @@ __global__ __launch_bounds__(kThreads) void k_colnorm_finish(StageArgs a) {
     // ||A_k(L)V||_{2,1} (eq:InductiveCNNM); the penalized program (eq:admm) adds
     // (lambda k / 2) ||P_Omega(L - M)||_F^2 (zero at initialisation, L = P_Omega M)
     double objective = ((sh_obj[0] + sh_obj[1]) + sh_obj[2]) + sh_obj[3];
-    if (I.lam <= 1e300) objective += 0.5 * I.lam * (double)a.k * sh_sc[2];
+    if (I.lam <= 1e300) objective += 0.5 * I.lam * (double)a.kt * sh_sc[2];
     const double maxn = fmax(fmax(sh_max[0], sh_max[1]), fmax(sh_max[2], sh_max[3]));
     int go = 1;
     if (phase == kInit) {
@@ -1509,7 +1509,7 @@ __global__ __launch_bounds__(kThreads) void k_colnorm_finish(StageArgs a) {
         go = 0;
       }
     } else {
-      const double kk = (double)a.k;
+      const double kk = (double)a.kt;
       st->r_primal = sqrt(sh_sc[0]) / (sqrt(kk) * st->denom);
       st->r_change = sqrt(sh_sc[1]) / st->denom;
       st->objective = objective;
@@ -1684,6 +1684,18 @@ __global__ void k_copy_f32(const float* src, float* dst, int64_t n) {
     dst[e] = src[e];
 }
 
+// V of the kernel (k0, k1, k2) into the bank of the kernel (k0, k1, k2p), k2p >= k2:
+// out[s'][i] = V[s][i] for the offset s' = (s0, s1, s2) with s2 < k2 and i < kt, else 0
+__global__ void k_pad_v(const float* V, int k0, int k1, int k2, int k2p, float* out) {
+  const int kt = k0 * k1 * k2, kc = k0 * k1 * k2p;
+  const int64_t n = (int64_t)kc * kc;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int sp = (int)(e / kc), i = (int)(e - (int64_t)sp * kc);
+    const int s2 = sp % k2p, s01 = sp / k2p;
+    out[e] = (s2 < k2 && i < kt) ? V[(int64_t)(s01 * k2 + s2) * kt + i] : 0.f;
+  }
+}
+
 __global__ void k_fill_f32(float* dst, float v, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
     dst[e] = v;
@@ -1784,6 +1796,11 @@ void launch_gram_expand(const double* R, const int32_t* k, double* G, hipStream_
 
 void launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_copy_f32, dim3(grid_for(n, 8192)), dim3(kThreads), 0, st, src, dst, n);
+}
+
+void launch_pad_v(const float* V, const int* kd, const int* kdp, float* out, hipStream_t st) {
+  const int64_t kc = (int64_t)kdp[0] * kdp[1] * kdp[2];
+  hipLaunchKernelGGL(k_pad_v, dim3(grid_for(kc * kc, 8192)), dim3(kThreads), 0, st, V, kd[0], kd[1], kd[2], kdp[2], out);
 }
 
 void launch_fill_f32(float* dst, float v, int64_t n, hipStream_t st) {

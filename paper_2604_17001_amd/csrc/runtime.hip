@@ -342,12 +342,25 @@ static int round_kind(int r, int prec, int max_iter, int refresh_every) {
   return (r - 1) % refresh_every == 0 ? (int)kFP32 : prec;
 }
 
+// Kernel dimensions the contractions run with. The reduced-precision forward reads
+// runs of four consecutive innermost kernel offsets, so for BF16/FP16 the innermost
+// kernel extent is padded to a multiple of 4 with offsets whose rows of V are zero:
+// A_k'(L) V' = A_k(L) V and A_k'^*(X V'^T) = A_k^*(X V^T) exactly, and the L-step
+// keeps dividing by the true k. FP32 runs the kernel as given.
+static void contraction_dims(const int kd[3], int prec, int kdp[3]) {
+  for (int d = 0; d < 3; ++d) kdp[d] = kd[d];
+  if (prec != kFP32) kdp[2] = (kd[2] + 3) / 4 * 4;
+}
+
 struct Group {
   Budget* budget;
-  int kd[3];
-  int k, kp, nsg, ncg, prec;
+  int kd[3];   // contraction kernel dimensions (innermost padded for BF16/FP16)
+  int kdt[3];  // the kernel's own dimensions
+  int k, kt;   // offsets of the contraction kernel; of the kernel itself (the 1/k of the L-step)
+  int kp, nsg, ncg, prec;
   const float* Vsrc = nullptr;
   DevBuf Vf, Va, Vp, Vlo_f, Vlo_a, Vlo_p;
+  DevBuf Vpad;  // V with the zero rows and columns of padded kernel offsets
   bool big = false;  // adjoint tiled for operand reuse: kp a multiple of 256, 128-row tiles
   std::vector<Member*> members;
   int capacity;
@@ -375,8 +388,10 @@ struct Group {
   Prof* prof = nullptr;
 
   Group(Budget* b, const int kdim[3], int prec_, int cap) : budget(b), prec(prec_), capacity(cap) {
-    for (int d = 0; d < 3; ++d) kd[d] = kdim[d];
+    for (int d = 0; d < 3; ++d) kdt[d] = kdim[d];
+    contraction_dims(kdt, prec, kd);
     k = kd[0] * kd[1] * kd[2];
+    kt = kdt[0] * kdt[1] * kdt[2];
     kp = padded_k(k);
     nsg = (kp + kGroup - 1) / kGroup;
     ncg = nsg;
@@ -396,6 +411,11 @@ struct Group {
 
   void set_v(const float* V, hipStream_t st) {
     Vsrc = V;
+    if (kt != k) {
+      Vpad.ensure(budget, (size_t)k * k * 4);
+      launch_pad_v(V, kdt, kd, Vpad.as<float>(), st);
+      V = Vpad.as<float>();
+    }
     const size_t n = (size_t)kp * kp;
     Vf.ensure(budget, n * 4);
     Va.ensure(budget, n * 4);
@@ -549,6 +569,7 @@ struct Group {
     a.Vp_lo = Vlo_p.p;
     a.kp = kp;
     a.k = k;
+    a.kt = kt;
     a.nsg = nsg;
     a.ncg = ncg;
     a.ntiles = ntiles_total;
@@ -851,10 +872,17 @@ static void check_params(const icnnm_params* p) {
   if (p->precision != 0 && p->refresh_every < 1) throw Error(ICNNM_E_INVALID, "refresh_every must be >= 1");
 }
 
-// the reduced-precision forward reads runs of four consecutive innermost kernel offsets
-static void check_precision_shape(const int kd[3], const icnnm_params* p) {
-  if (p->precision != 0 && kd[2] % 4 != 0)
-    throw Error(ICNNM_E_INVALID, "BF16/FP16 contractions need the innermost kernel dimension to be a multiple of 4");
+// the reduced precisions pad the innermost kernel extent to a multiple of 4 (see
+// contraction_dims); the padded kernel must still fit the tensor
+static void check_precision_shape(const int m[3], const int kd[3], const icnnm_params* p) {
+  int kdp[3];
+  contraction_dims(kd, p->precision, kdp);
+  if (kdp[2] > m[2])
+    throw Error(ICNNM_E_INVALID, "BF16/FP16 contractions pad the innermost kernel extent to a multiple of 4 (" +
+                                     std::to_string(kdp[2]) + "), which must not exceed the innermost tensor extent (" +
+                                     std::to_string(m[2]) + ")");
+  if ((int64_t)kdp[0] * kdp[1] * kdp[2] > 4096)
+    throw Error(ICNNM_E_INVALID, "padded kernel size above 4096 is not supported");
 }
 
 static void check_v(icnnm_ctx* c, const float* V, int k, hipStream_t st) {
@@ -987,14 +1015,16 @@ static double time_plan(icnnm_ctx* c, const Plan& p, const int kd[3], int prec, 
 static Plan choose_plan(icnnm_ctx* c, const int m[3], const int kd[3], int kp, int prec, const float* M,
                         const uint8_t* mask, const float* V, hipStream_t st, bool same_class,
                         bool may_measure = true) {
-  auto base_plan = [&] { return same_class ? make_plan_shared(m, kd, kp) : make_plan(m, kd, kp); };
+  int kdp[3];
+  contraction_dims(kd, prec, kdp);
+  auto base_plan = [&] { return same_class ? make_plan_shared(m, kdp, kp) : make_plan(m, kdp, kp); };
   if (!autotune_on() || getenv("ICNNM_TILE")) return base_plan();
   load_tune_cache(c);
   const std::string key = tune_key(m, kd, prec, same_class ? 1 : 0);
   auto it = c->tuned.find(key);
-  if (it != c->tuned.end()) return plan_with_box(m, kd, kp, it->second.data());
+  if (it != c->tuned.end()) return plan_with_box(m, kdp, kp, it->second.data());
   if (!may_measure) return base_plan();
-  auto all = plan_candidates(m, kd, kp);
+  auto all = plan_candidates(m, kdp, kp);
   if (all.empty()) throw Error(ICNNM_E_INVALID, "no tile shape fits this problem");
   std::vector<Plan> cands;
   const Plan first = base_plan();
@@ -1042,7 +1072,7 @@ static icnnm_status do_solve(icnnm_ctx* c, const icnnm_shape* shape, const float
   int m[3], kd[3];
   normalize_shape(shape, m, kd);
   check_params(params);
-  check_precision_shape(kd, params);
+  check_precision_shape(m, kd, params);
   if (!M || !mask || !V || !L_out) throw Error(ICNNM_E_INVALID, "NULL array argument");
   std::lock_guard<std::recursive_mutex> lock(c->mu);
   hipStream_t st = enter(c, user_stream);
@@ -1139,7 +1169,7 @@ static icnnm_status do_solve_batch(icnnm_ctx* c, int count, const icnnm_shape* s
     int m[3], kd[3];
     normalize_shape(&shapes[i], m, kd);
     if (i == 0) std::copy(kd, kd + 3, kd0);
-    check_precision_shape(kd, params);
+    check_precision_shape(m, kd, params);
     if (!std::equal(kd, kd + 3, kd0)) throw Error(ICNNM_E_INVALID, "batch instances must share the kernel size");
     if (!Ms[i] || !masks[i] || !Louts[i]) throw Error(ICNNM_E_INVALID, "NULL array in batch");
     auto mb = std::make_unique<Member>();
@@ -1153,7 +1183,7 @@ static icnnm_status do_solve_batch(icnnm_ctx* c, int count, const icnnm_shape* s
   std::lock_guard<std::recursive_mutex> lock(c->mu);
   hipStream_t st = enter(c, user_stream);
   Group g(&c->budget, kd0, params->precision, count);
-  if (params->check_v) check_v(c, V, g.k, st);
+  if (params->check_v) check_v(c, V, g.kt, st);
   for (int i = 0; i < count; ++i) {
     int m[3], kd[3];
     normalize_shape(&shapes[i], m, kd);
@@ -1255,17 +1285,20 @@ static icnnm_status do_solve_noalloc(icnnm_ctx* c, const icnnm_shape* shape, con
   int m[3], kd[3];
   normalize_shape(shape, m, kd);
   check_params(params);
-  check_precision_shape(kd, params);
+  check_precision_shape(m, kd, params);
   if (!M || !mask || !V || !L_out) throw Error(ICNNM_E_INVALID, "NULL array argument");
   if (!c->scratch) throw Error(ICNNM_E_DEVICE, "allocation-free scratch unavailable: " + c->scratch_err);
   const int k = kd[0] * kd[1] * kd[2];
-  const int kp = padded_k(k), nsg = (kp + kGroup - 1) / kGroup;
+  int kdp[3];
+  contraction_dims(kd, params->precision, kdp);
+  const int kc = kdp[0] * kdp[1] * kdp[2];
+  const int kp = padded_k(kc), nsg = (kp + kGroup - 1) / kGroup;
   Budget arena;  // outlives every buffer carved from it
   arena.arena = c->scratch;
   arena.limit = kNoAllocBytes;
   Member mb;
-  mb.plan = make_plan(m, kd, kp);  // the cost model's box (no measurement: it would allocate)
-  const size_t need = noalloc_bytes(mb.plan, kp, nsg, params->precision);
+  mb.plan = make_plan(m, kdp, kp);  // the cost model's box (no measurement: it would allocate)
+  const size_t need = noalloc_bytes(mb.plan, kp, nsg, params->precision) + (kc != k ? (size_t)kc * kc * 4 + 256 : 0);
   if (need > kNoAllocBytes)
     throw Error(ICNNM_E_BUDGET, "instance needs " + std::to_string(need) + " bytes of solver state, above the " +
                                     std::to_string(kNoAllocBytes >> 20) + " MiB allocation-free scratch maximum");
@@ -1515,10 +1548,11 @@ icnnm_status icnnm_plan(const icnnm_shape* shape, const icnnm_params* params, in
     int m[3], kd[3];
     normalize_shape(shape, m, kd);
     check_params(params);
-    check_precision_shape(kd, params);
-    const int k = kd[0] * kd[1] * kd[2];
-    const int kp = padded_k(k), nsg = (kp + kGroup - 1) / kGroup;
-    const Plan p = joint ? make_plan_shared(m, kd, kp) : make_plan(m, kd, kp);
+    check_precision_shape(m, kd, params);
+    int kdp[3];
+    contraction_dims(kd, params->precision, kdp);
+    const int kp = padded_k(kdp[0] * kdp[1] * kdp[2]), nsg = (kp + kGroup - 1) / kGroup;
+    const Plan p = joint ? make_plan_shared(m, kdp, kp) : make_plan(m, kdp, kp);
     for (int d = 0; d < 3; ++d) {
       out->tile[d] = p.b[d];
       out->tiles_per_dim[d] = p.nt[d];
@@ -1678,7 +1712,7 @@ static void serve_loop(icnnm_ctx* c) {
           sg.g->set_v(r.V, sg.stream);
         }
         auto mb = std::make_unique<Member>();
-        mb->plan = make_plan_shared(r.m, r.kd, sg.g->kp);
+        mb->plan = make_plan_shared(r.m, sg.g->kd, sg.g->kp);
         mb->params = r.params;
         mb->M = r.M;
         mb->mask = r.mask;
@@ -1779,7 +1813,7 @@ static icnnm_status do_submit(icnnm_ctx* c, const icnnm_shape* shape, const floa
   Request r{};
   normalize_shape(shape, r.m, r.kd);
   check_params(params);
-  check_precision_shape(r.kd, params);
+  check_precision_shape(r.m, r.kd, params);
   if (!M || !mask || !V || !L_out) throw Error(ICNNM_E_INVALID, "NULL array argument");
   r.shape = *shape;
   r.M = M;
@@ -1789,9 +1823,12 @@ static icnnm_status do_submit(icnnm_ctx* c, const icnnm_shape* shape, const floa
   r.Lout = L_out;
   r.t_submit = now_s();
   const int k = r.kd[0] * r.kd[1] * r.kd[2];
-  const int kp = padded_k(k);
+  int kdp[3];
+  contraction_dims(r.kd, params->precision, kdp);
+  const int kc = kdp[0] * kdp[1] * kdp[2];
+  const int kp = padded_k(kc);
   const int nsg = (kp + kGroup - 1) / kGroup;
-  const Plan p = make_plan_shared(r.m, r.kd, kp);  // as the server will plan it
+  const Plan p = make_plan_shared(r.m, kdp, kp);  // as the server will plan it
   // the member's state, plus its entries in the group's descriptor and tile tables
   // (which grow by doubling)
   r.bytes = member_bytes(p, kp, nsg, nsg, params->precision) +
@@ -1799,7 +1836,7 @@ static icnnm_status do_submit(icnnm_ctx* c, const icnnm_shape* shape, const floa
   // a new group: V operand copies (three FP32 layouts, three more in BF16/FP16 for the
   // reduced precisions) and the state array of its slots
   r.group_bytes = align256((size_t)kp * kp * 4) * 3 + (params->precision != 0 ? 3 * align256((size_t)kp * kp * 2) : 0) +
-                  align256(sizeof(InstState) * kServeSlots);
+                  align256(sizeof(InstState) * kServeSlots) + (kc != k ? align256((size_t)kc * kc * 4) : 0);
   r.bypassed = 0;
   if (r.bytes + r.group_bytes > c->budget.limit) throw Error(ICNNM_E_BUDGET, "request alone exceeds the HBM budget");
   if (params->check_v) {

@@ -93,11 +93,45 @@ def test_refresh_improves_accuracy(lib):
     assert errs[80] > 10 * errs[5]
 
 
-def test_precision_needs_innermost_kernel_multiple_of_4(lib):
-    prob, V32 = _case((12, 10, 8), (3, 3, 2), 0.4, 6)
+def test_padded_kernel_must_fit_the_tensor(lib):
+    # the reduced precisions pad the innermost kernel extent to a multiple of 4; a
+    # 3x3x3 kernel on a tensor whose innermost extent is 3 cannot be padded to 4
+    prob, V32 = _case((12, 10, 3), (3, 3, 3), 0.4, 6)
     with pytest.raises(icnnm.IcnnmError) as ei:
         lib.solve(_dev(prob.M), _dev(prob.mask), _dev(V32), prob.kdims, max_iter=5, precision="bf16")
     assert ei.value.code == icnnm.E_INVALID
+    L, _ = lib.solve(_dev(prob.M), _dev(prob.mask), _dev(V32), prob.kdims, max_iter=5)  # FP32 runs it as given
+
+
+# The paper's image and video kernels (Section V: square kernels 13x13 .. 43x43 on
+# images, 13x13x13 on videos) in the reduced precisions: the innermost kernel extent
+# (13 or 43) is padded to a multiple of 4 with zero rows of V, the L-step keeps the
+# true k. Iteration counts include an FP32 refresh in the middle (iteration 11).
+PAPER_K = [((64, 64), (13, 13), 0.5, 31, 24), ((64, 64), (43, 43), 0.5, 32, 12),
+           ((20, 20, 16), (13, 13, 13), 0.4, 33, 12), ((30, 7), (5, 3), 0.4, 34, 30)]
+_ORACLE = {}
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("dims,kdims,pm,seed,iters", PAPER_K)
+def test_reduced_precision_paper_kernels(lib, prec, dims, kdims, pm, seed, iters):
+    key = (dims, kdims, seed, iters)
+    if key not in _ORACLE:
+        prob, V32 = _case(dims, kdims, pm, seed, b=2)
+        Lo, _ = O.solve(prob.M, prob.mask, V32.astype(np.float64), kdims, iters)
+        _ORACLE[key] = (prob, V32, Lo)
+    prob, V32, Lo = _ORACLE[key]
+    print(f"[gpu] {prec} paper kernel dims={dims} kdims={kdims} iters={iters}", flush=True)
+    L, info = lib.solve(_dev(prob.M), _dev(prob.mask), _dev(V32), kdims, max_iter=iters, precision=prec)
+    L = L.cpu().numpy()
+    err = _rel(L, Lo)
+    print(f"[gpu] {prec} rel.err {err:.3e}", flush=True)
+    assert info["iters"] == iters
+    assert err <= TOL_LP
+    assert np.array_equal(L[prob.mask != 0], prob.M[prob.mask != 0])
+    # the same padded kernel in a joint (batch) launch
+    (Lb,), _ = lib.solve_batch([_dev(prob.M)], [_dev(prob.mask)], _dev(V32), kdims, max_iter=iters, precision=prec)
+    assert _rel(Lb.cpu().numpy(), Lo) <= TOL_LP
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])

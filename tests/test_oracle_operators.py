@@ -114,3 +114,28 @@ def test_pins_catch_unshifted_adjoint():
     bad_adj = X.sum(axis=1).reshape(dims)       # forgot to shift the columns back
     lhs = float(np.sum(O.conv_matrix(L, kdims) * X))
     assert abs(lhs - float(np.sum(L * bad_adj))) > 1e-3
+
+
+def test_zero_padded_kernel_offsets_change_nothing():
+    # Padding the innermost kernel extent (13 -> 16) with offsets whose rows of V are
+    # zero leaves A_k(L)V and A_k^*(X V^T) unchanged: the padded offsets' columns of the
+    # convolution matrix meet zero rows of V, and the adjoint of a zero column is zero.
+    # (The reduced-precision contractions rely on this; the L-step keeps the true k.)
+    rng = np.random.default_rng(5)
+    dims, kd, kdp = (9, 20), (3, 13), (3, 16)
+    L = rng.standard_normal(dims)
+    k, kc = 3 * 13, 3 * 16
+    V = np.linalg.qr(rng.standard_normal((k, k)))[0]
+    Vp = np.zeros((kc, kc))
+    for s0 in range(3):
+        for s1 in range(13):
+            Vp[s0 * 16 + s1, :k] = V[s0 * 13 + s1]
+    W = O.conv_matrix(L, kd) @ V
+    Wp = O.conv_matrix(L, kdp) @ Vp
+    assert np.allclose(Wp[:, :k], W, atol=1e-12) and np.abs(Wp[:, k:]).max() == 0.0
+    X = rng.standard_normal((L.size, k))
+    Xp = np.zeros((L.size, kc))
+    Xp[:, :k] = X
+    assert np.allclose(O.adjoint(Xp @ Vp.T, dims, kdp), O.adjoint(X @ V.T, dims, kd), atol=1e-12)
+    # but A_k'^* A_k' = k' I: the L-step must divide by the true k
+    assert np.allclose(O.adjoint(O.conv_matrix(L, kdp), dims, kdp), kc * L)

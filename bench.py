@@ -41,10 +41,8 @@ METRIC = "solved tensors/s at rel.err\u22641e-3 vs FP64 oracle; p50/p99 latency;
 # the same counters on a plain 256 MiB copy (fetch x2.0, write x1.0); valid only for the
 # kernel source they were taken on (sha256 prefix of kernels.hip)
 TRAFFIC = {
-    ("64x64x16", "fp32", "forward"): {"bytes": 284.7e6, "src": "0331dca4bd7903ee"},
-    ("64x64x16", "fp32", "adjoint"): {"bytes": 139.3e6, "src": "0331dca4bd7903ee"},
-    ("128x128x32", "bf16", "forward"): {"bytes": 9.86e9, "src": "0331dca4bd7903ee"},
-    ("128x128x32", "bf16", "adjoint"): {"bytes": 5.63e9, "src": "0331dca4bd7903ee"},
+    ("batch", "bf16", "forward"): {"bytes": 28.08e9, "src": "2799daf8f9b4fc17"},
+    ("batch", "bf16", "adjoint"): {"bytes": 13.60e9, "src": "2799daf8f9b4fc17"},
 }
 
 
@@ -131,6 +129,14 @@ def _calibrate_copy():
     del x, y
 
 
+def _state_bytes(precision, m, kp):
+    """Algorithmic state bytes per launch of the forward (reads and writes W and the
+    multiplier U) and of the adjoint (reads them) over m x kp state entries: W is FP32;
+    U is FP32 in the FP32 form and BF16 in the reduced-precision forms."""
+    per = 4.0 + (4.0 if precision == "fp32" else 2.0)
+    return {"forward": 2.0 * per * m * kp, "adjoint": per * m * kp}
+
+
 def _padded_k(k):
     return ((k + 63) // 64) * 64 if k <= 256 else ((k + 255) // 256) * 256
 
@@ -215,7 +221,7 @@ def _headline(args):
         stages = _stage_avgs(lib.stage_times(reset=True, split=True))
         kp = _padded_k(k)
         part = "lowp" if prec != "fp32" else "fp32"
-        cand = {"forward": 16.0 * msum * kp, "adjoint": 8.0 * msum * kp}
+        cand = _state_bytes(prec, msum, kp)
         dom = max(cand, key=lambda s: stages.get(f"{s}_{part}", {"avg_us": 0.0})["avg_us"])
         tr = TRAFFIC.get(("batch", prec, dom))
         traffic = tr["bytes"] if tr and tr["src"] == _kernel_src_hash() and iters == wl.iters else None
@@ -534,9 +540,7 @@ def main():
         stages = _stage_avgs(lib.stage_times(reset=True, split=True))
         part = "fp32" if args.precision == "fp32" else "lowp"
         kp = _padded_k(k)
-        # algorithmic state bytes per launch: the forward reads and writes U and Q, the
-        # adjoint reads them (FP32, m x kp entries each)
-        cand = {"forward": 16.0 * m * kp, "adjoint": 8.0 * m * kp}
+        cand = _state_bytes(args.precision, m, kp)
         dom = max(cand, key=lambda s_: stages.get(f"{s_}_{part}", {"avg_us": 0.0})["avg_us"])
         tr = TRAFFIC.get((args.workload, args.precision, dom))
         traffic = tr["bytes"] if tr and tr["src"] == _kernel_src_hash() and args.iters == 0 else None

@@ -2,7 +2,7 @@
 //
 // One ADMM iteration (Section III-D) runs as four stage kernels over a table
 // of spatial tiles that may span many instances:
-//   colnorm : FP64 column norms of Q -> shrink factors s_i (Z-step), penalty
+//   colnorm : FP64 column norms of Q = W - U -> shrink factors s_i (Z-step), penalty
 //             schedule, stopping residuals of the previous iteration
 //   adjoint : G = U + s.Q (scaled Y + theta Z), H = G V^T on MFMA, col2im of H
 //             into an LDS box (transposed convolutions summed back)
@@ -57,8 +57,9 @@ struct alignas(16) InstDev {
   const uint8_t* mask;
   float* L;         // current iterate (C order)
   float* D;         // reduced precision: L^t - L^{t-1}, the operand of the delta forward
-  float* U;         // scaled dual Y / theta, tile layout
-  float* Q;         // W - U, tile layout
+  void* U;          // scaled multiplier Y / theta, tile layout: FP32, or BF16 in the
+                    // reduced-precision forms (16-byte chunks of eight values)
+  float* W;         // A_k(L) V of the current iterate, tile layout, FP32 (Q = W - U)
   float* part;      // adjoint halo partials [ntiles][nsg][E123]
   float* qpart;     // [ntiles][kp] per-tile sums of Q^2
   float* wpart;     // [ntiles][kp] per-tile sums of W^2
@@ -85,6 +86,7 @@ struct StageArgs {
   int32_t kp, k, nsg, ncg;  // k: offsets of the contraction kernel (innermost extent
                             // padded to a multiple of 4 in BF16/FP16)
   int32_t kt;               // offsets of the kernel itself: the 1/k of the L-step
+  int32_t u16;              // U stored in 16 bits (the instances' precision is BF16/FP16)
   int32_t ntiles;        // entries of `tiles`
   int32_t tiles_per_slice;
   int32_t prec;

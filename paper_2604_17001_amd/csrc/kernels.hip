@@ -3,13 +3,14 @@
 // Operators (Section II-B, Section III-D):
 //   A_k(L)[i, s] = L[(i - s) mod m]           convolution matrix (eq:ak)
 //   A_k^*(X)[t]  = sum_s X[(t + s) mod m, s]   its adjoint
-// The m x k state arrays (scaled dual U and Q = W - U) are stored in "tile
-// layout": for each 32-row group of a tile and each 32-column block, the 1024
-// values are the 32x32 MFMA accumulator's, as 256 float4: float4 g (accumulator
-// values 4g..4g+3) of lane l at position g * 64 + l. A lane reads and writes its
-// 16 values as four 16-byte accesses, each of which is one contiguous kilobyte
-// over the wavefront, and the adjoint consumes them directly as its B operand
-// without a transpose.
+// The m x k state arrays (W = A_k(L) V and the scaled multiplier U = Y / theta;
+// the Z-step operand Q = W - U is derived on load) are stored in "tile layout":
+// for each 32-row group of a tile and each 32-column block, the 1024 values are
+// the 32x32 MFMA accumulator's, as 256 float4: float4 g (accumulator values
+// 4g..4g+3) of lane l at position g * 64 + l. A lane reads and writes its 16
+// values as four 16-byte accesses, each of which is one contiguous kilobyte over
+// the wavefront, and the adjoint consumes them directly as its B operand without
+// a transpose. In the reduced-precision forms U is BF16 (see u16_unpack).
 //
 // Accumulator layout of v_mfma_f32_32x32x2_f32 for D = A(32 x 2) B(2 x 32):
 //   lane l, register v holds D[(v/4)*8 + (l/32)*4 + v%4][l%32];
@@ -247,17 +248,47 @@ __device__ __forceinline__ float half_sum16(float (&v)[16], int lane, int& vi) {
   return v[0];
 }
 
+// 16-bit storage of the scaled multiplier U in the reduced-precision forms (UB = 2):
+// BF16, eight values per 16-byte chunk. A piece (32 rows x 32 columns of the tile
+// layout) is 128 chunks: chunk c of lane l, values 8c..8c+7 of the lane's accumulator
+// order, at c * 64 + l, so each access is one contiguous kilobyte over the wavefront.
+__device__ __forceinline__ void u16_unpack(const uint4 h, float* v) {
+  const uint32_t w[4] = {h.x, h.y, h.z, h.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[2 * i] = __uint_as_float(w[i] << 16);
+    v[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+  }
+}
+__device__ __forceinline__ uint32_t u16_bits(float x) {
+  __bf16 b = (__bf16)x;  // round to nearest even
+  uint16_t r;
+  __builtin_memcpy(&r, &b, 2);
+  return r;
+}
+__device__ __forceinline__ uint4 u16_pack(const float* v) {
+  uint32_t w[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w[i] = u16_bits(v[2 * i]) | (u16_bits(v[2 * i + 1]) << 16);
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+// the value a stored 16-bit U reads back as
+__device__ __forceinline__ float u16_round(float x) { return __uint_as_float(u16_bits(x) << 16); }
+
 // =====================================================================================
-// forward: W = A_k(L) V, fused with the dual update and the next Q.
-//   init (phase kInit): U = 0, Q = W                      (Y^0 = 0)
+// forward: W = A_k(L) V, fused with the dual update.
+// The per-instance state is W (FP32) and the scaled multiplier U = Y / theta (FP32, or
+// BF16 in the reduced-precision forms: UB = 2); Q = W - U is derived on load.
+//   init (phase kInit): U = 0, W                             (Y^0 = 0)
 //   run  (phase kRun):  Z = s.Q_old, G = U_old + Z,
-//                       U = (G - W) theta/theta',  Q = W - U
+//                       U = (G - W) theta/theta',  Q = W - U (with U as stored)
 // and per-tile partial sums of Q^2, W^2 (per column) and (Z - W)^2.
 // grid = (tiles, kp / 256 column groups); each wave takes (64 rows x 64 columns) units.
 // =====================================================================================
-template <int MODE, int RB>
+template <int MODE, int RB, int UB>
 __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   static_assert(RB == 2 || (RB == 4 && MODE != kFP32), "FP32 units have two row blocks");
+  static_assert(UB == 4 || UB == 2, "U is stored in 32 or 16 bits");
   extern __shared__ float smem[];
   const int2 tt = a.tiles[blockIdx.x];
   const InstDev& I = a.inst[tt.x];
@@ -369,6 +400,42 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
     int base[RB];
 #pragma unroll
     for (int ib = 0; ib < RB; ++ib) base[ib] = row_base(ru * RB * 32 + ib * 32 + (lane & 31), I, o, valid[ib]);
+
+    // U/Q loads of the fused epilogue over the 2 RB 32x32 pieces (cb, ib) of the unit.
+    // Reduced precision with 64-row units: all four pieces are loaded at the start of
+    // the unit, so their HBM latency overlaps the contraction (the accumulators take
+    // only 64 registers there). Otherwise a piece's loads are issued one or two pieces
+    // ahead, overlapping the arithmetic and stores of the pieces before it.
+    constexpr int kPieces = 2 * RB;
+    constexpr bool kEarly = MODE != kFP32 && RB == 2;
+    constexpr int kAhead = kEarly ? kPieces : (RB == 4 ? 1 : 2);  // pieces of U/Q loads in flight
+    float rsum[kRpu];
+#pragma unroll
+    for (int r = 0; r < kRpu; ++r) rsum[r] = 0.f;
+    // bw: W of a piece (four float4); bu: U (four float4 in FP32, two raw chunks in BF16)
+    float4 bw[kAhead][4];
+    typedef typename std::conditional<UB == 4, float4[4], uint4[2]>::type UPiece;
+    UPiece bu[kAhead];
+    auto load_piece = [&](int pc, int slot) {
+      const int cb = pc / RB, ib = pc % RB;
+      const size_t pidx = ((size_t)lt * (I.bm / 32) + ru * RB + ib) * nkb + c0 / 32 + cb;
+      gcfloat4* Wp = gc4(I.W) + pidx * 256 + lane;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) bw[slot][g] = Wp[g * 64];
+      if constexpr (UB == 4) {
+        gcfloat4* Up = gc4(I.U) + pidx * 256 + lane;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) bu[slot][g] = Up[g * 64];
+      } else {
+        gcuint4* Up = gcu4(I.U) + pidx * 128 + lane;
+        bu[slot][0] = Up[0];
+        bu[slot][1] = Up[64];
+      }
+    };
+    if constexpr (kEarly) {
+#pragma unroll
+      for (int i = 0; i < kPieces; ++i) load_piece(i, i);
+    }
 
     floatx16 acc[2][RB];
 #pragma unroll
@@ -505,33 +572,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
     }
     }
 
-    // fused epilogue over the 2 RB 32x32 pieces (cb, ib) of the unit; the U/Q loads
-    // of a piece are issued two pieces ahead so that their latency overlaps the
-    // arithmetic and stores of the pieces before it
-    constexpr int kPieces = 2 * RB;
-    constexpr int kAhead = RB == 4 ? 1 : 2;  // pieces of U/Q loads in flight
-    float rsum[kRpu];
-#pragma unroll
-    for (int r = 0; r < kRpu; ++r) rsum[r] = 0.f;
-    float4 bu[kAhead][4], bq[kAhead][4];
-    auto load_piece = [&](int pc, int slot) {
-      const int cb = pc / RB, ib = pc % RB;
-      const size_t sidx = (((size_t)lt * (I.bm / 32) + ru * RB + ib) * nkb + c0 / 32 + cb) * 256 + lane;
-      gcfloat4* Up = gc4(I.U) + sidx;
-      gcfloat4* Qp = gc4(I.Q) + sidx;
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        bu[slot][g] = Up[g * 64];
-        bq[slot][g] = Qp[g * 64];
-      }
-    };
     // Two compiled forms of the same arithmetic: the first forward of a solve (U = 0,
     // Q = W, nothing loaded) and every later one. FP32: rows past the tensor's end
     // get W = 0; their U and Q are zero from the first forward on, so every value
     // derived from them is zero as well without further masking.
     auto epilogue = [&](auto init_c) {
       constexpr bool kFirst = decltype(init_c)::value;
-      if constexpr (!kFirst) {
+      if constexpr (!kFirst && !kEarly) {
 #pragma unroll
         for (int i = 0; i < kAhead; ++i) load_piece(i, i);
       }
@@ -550,44 +597,51 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
 #pragma unroll
         for (int ib = 0; ib < RB; ++ib) {
           const int pc = cb * RB + ib, slot = pc % kAhead;
-          float4 u4s[4], q4s[4];
+          // the piece's old U, unpacked from BF16 (UB = 2; FP32 U is read in place)
+          float u16v[UB == 2 ? 16 : 1];
+          float4 wo4[4], uo4[4];
 #pragma unroll
-          for (int g = 0; g < 4; ++g) {
-            u4s[g] = make_float4(0.f, 0.f, 0.f, 0.f);
-            q4s[g] = u4s[g];
-            if constexpr (!kFirst) {
-              u4s[g] = bu[slot][g];
-              q4s[g] = bq[slot][g];
-            }
-          }
+          for (int g = 0; g < 4; ++g) wo4[g] = uo4[g] = make_float4(0.f, 0.f, 0.f, 0.f);
           if constexpr (!kFirst) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g) wo4[g] = bw[slot][g];
+            if constexpr (UB == 4) {
+#pragma unroll
+              for (int g = 0; g < 4; ++g) uo4[g] = bu[slot][g];
+            } else {
+              u16_unpack(bu[slot][0], u16v);
+              u16_unpack(bu[slot][1], u16v + 8);
+#pragma unroll
+              for (int g = 0; g < 4; ++g) uo4[g] = make_float4(u16v[4 * g], u16v[4 * g + 1], u16v[4 * g + 2], u16v[4 * g + 3]);
+            }
             if (pc + kAhead < kPieces) load_piece(pc + kAhead, slot);
           }
-          const size_t sidx = (((size_t)lt * (I.bm / 32) + ru * RB + ib) * nkb + cblk) * 256 + lane;
-          gfloat4* Up = g4(I.U) + sidx;
-          gfloat4* Qp = g4(I.Q) + sidx;
+          const size_t pidx = ((size_t)lt * (I.bm / 32) + ru * RB + ib) * nkb + cblk;
+          gfloat4* Wp = g4(I.W) + pidx * 256 + lane;
+          gfloat4* Up4 = g4(I.U) + pidx * 256 + lane;
+          float unv[UB == 2 ? 16 : 1];
 #pragma unroll
           for (int g = 0; g < 4; ++g) {
-            const float4 u4 = u4s[g], q4 = q4s[g], sv4 = s4[g];
-            const float uo[4] = {u4.x, u4.y, u4.z, u4.w}, qo[4] = {q4.x, q4.y, q4.z, q4.w};
+            const float4 u4 = uo4[g], w4 = wo4[g], sv4 = s4[g];
+            const float uo[4] = {u4.x, u4.y, u4.z, u4.w}, wo[4] = {w4.x, w4.y, w4.z, w4.w};
             const float sv[4] = {sv4.x, sv4.y, sv4.z, sv4.w};
-            float un[4], qn[4];
+            float un[4], wn[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-              // Z = s.Q_old, U = (U_old + Z - W) ratio, Q = W - U; residual (Z - W)^2
-              float w, unew, qnew;
+              // Q_old = W_old - U_old; Z = s.Q_old, U = (U_old + Z - W) ratio, Q = W - U;
+              // residual (Z - W)^2
+              const float qo = wo[e] - uo[e];
+              float w, unew;
               if constexpr (MODE != kFP32) {
                 // W^t = W^{t-1} + A_k(L^t - L^{t-1}) V; this form (masking after the
                 // update) schedules better in the HBM-bound reduced-precision kernels
-                w = acc[cb][ib][4 * g + e] + (uo[e] + qo[e]);
+                w = acc[cb][ib][4 * g + e] + wo[e];
                 if (!valid[ib]) {
                   w = 0.f;
                   unew = 0.f;
-                  qnew = 0.f;
                 } else {
-                  const float z = sv[e] * qo[e];
+                  const float z = sv[e] * qo;
                   unew = ((uo[e] + z) - w) * ratio;
-                  qnew = w - unew;
                   const float d = z - w;
                   rsum[ib / 2] += d * d;
                 }
@@ -595,21 +649,30 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
                 w = valid[ib] ? acc[cb][ib][4 * g + e] : 0.f;
                 if constexpr (kFirst) {
                   unew = 0.f;
-                  qnew = w;
                 } else {
-                  const float d = sv[e] * qo[e] - w;
+                  const float d = sv[e] * qo - w;
                   unew = (uo[e] + d) * ratio;
-                  qnew = w - unew;
                   rsum[ib / 2] += d * d;
                 }
               }
+              // the column norms see Q as the next iteration will derive it
+              if constexpr (UB == 2) {
+                unew = u16_round(unew);
+                unv[4 * g + e] = unew;
+              }
+              const float qnew = w - unew;
               un[e] = unew;
-              qn[e] = qnew;
+              wn[e] = w;
               qs[4 * g + e] += qnew * qnew;
               ws[4 * g + e] += w * w;
             }
-            Up[g * 64] = make_float4(un[0], un[1], un[2], un[3]);
-            Qp[g * 64] = make_float4(qn[0], qn[1], qn[2], qn[3]);
+            Wp[g * 64] = make_float4(wn[0], wn[1], wn[2], wn[3]);
+            if constexpr (UB == 4) Up4[g * 64] = make_float4(un[0], un[1], un[2], un[3]);
+          }
+          if constexpr (UB == 2) {
+            uint4* Up = reinterpret_cast<uint4*>(I.U) + pidx * 128 + lane;
+            Up[0] = u16_pack(unv);
+            Up[64] = u16_pack(unv + 8);
           }
           // FP32: one piece at a time (keeps the scheduler from hoisting the loads of
           // later pieces, which costs registers)
@@ -811,7 +874,29 @@ struct GatherAcc<8, CAP> {
   }
 };
 
-template <int MODE, int GV>
+// Loads of the state for the adjoint's G: the eight values 8p..8p+7 of one lane (the
+// float4 groups 2p and 2p + 1 of the tile layout) of W and of U for the piece at
+// piece index pidx, with Q = W - U returned in place of W.
+template <int UB>
+__device__ __forceinline__ void load_uq8(const InstDev& I, size_t pidx, int p, int lane, float4 (&u)[2],
+                                         float4 (&q)[2]) {
+  gcfloat4* W4 = gc4(I.W) + pidx * 256 + 2 * p * 64 + lane;
+  const float4 w0 = W4[0], w1 = W4[64];
+  if constexpr (UB == 4) {
+    gcfloat4* U4 = gc4(I.U) + pidx * 256 + 2 * p * 64 + lane;
+    u[0] = U4[0];
+    u[1] = U4[64];
+  } else {
+    float v[8];
+    u16_unpack(gcu4(I.U)[pidx * 128 + p * 64 + lane], v);
+    u[0] = make_float4(v[0], v[1], v[2], v[3]);
+    u[1] = make_float4(v[4], v[5], v[6], v[7]);
+  }
+  q[0] = make_float4(w0.x - u[0].x, w0.y - u[0].y, w0.z - u[0].z, w0.w - u[0].w);
+  q[1] = make_float4(w1.x - u[1].x, w1.y - u[1].y, w1.z - u[1].z, w1.w - u[1].w);
+}
+
+template <int MODE, int GV, int UB>
 __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
   extern __shared__ float smem[];
   int2 tt;
@@ -838,8 +923,6 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
 
   const int nkb = kp / 32;
   const int nhb = 2 * nkb;  // half column blocks of 8 MFMA k-steps
-  gcfloat4* U4 = gc4(I.U);
-  gcfloat4* Q4 = gc4(I.Q);
   const float* S = I.s;
   for (int rd = 0; rd < rounds; ++rd) {
     const int u = rd * 4 + wave;
@@ -862,13 +945,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
     auto load = [&](int h) {
       const int cb = h >> 1, p = h & 1;
 #pragma unroll
-      for (int jb = 0; jb < 2; ++jb) {
-        const size_t o = (row0 + (size_t)jb * nkb + cb) * 256 + 2 * p * 64 + lane;
-        fu[jb][0] = U4[o];
-        fu[jb][1] = U4[o + 64];
-        fq[jb][0] = Q4[o];
-        fq[jb][1] = Q4[o + 64];
-      }
+      for (int jb = 0; jb < 2; ++jb) load_uq8<UB>(I, row0 + (size_t)jb * nkb + cb, p, lane, fu[jb], fq[jb]);
       fs[0] = *gc4(S + cb * 32 + (2 * p) * 8 + half * 4);
       fs[1] = *gc4(S + cb * 32 + (2 * p + 1) * 8 + half * 4);
       const size_t ov = (size_t)cb * 256 + 2 * p;
@@ -917,13 +994,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
     auto load = [&](int h) {
       const int cb = h >> 1, p = h & 1;
 #pragma unroll
-      for (int jb = 0; jb < 2; ++jb) {
-        const size_t o = (row0 + (size_t)jb * nkb + cb) * 256 + 2 * p * 64 + lane;
-        fu[jb][0] = U4[o];
-        fu[jb][1] = U4[o + 64];
-        fq[jb][0] = Q4[o];
-        fq[jb][1] = Q4[o + 64];
-      }
+      for (int jb = 0; jb < 2; ++jb) load_uq8<UB>(I, row0 + (size_t)jb * nkb + cb, p, lane, fu[jb], fq[jb]);
       fs[0] = *gc4(S + cb * 32 + (2 * p) * 8 + half * 4);
       fs[1] = *gc4(S + cb * 32 + (2 * p + 1) * 8 + half * 4);
       fv0 = va0[(size_t)h * 64];
@@ -982,7 +1053,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
 constexpr int kBigChunk = 16;            // eigendirections per staged chunk
 constexpr int kBigPad = kBigChunk + 1;   // LDS row stride (odd: conflict-free columns)
 
-template <int GV>
+template <int GV, int UB>
 __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big(StageArgs a) {
   extern __shared__ float smem[];
   int2 tt;
@@ -1008,8 +1079,6 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big(StageArgs a) {
 
   // cooperative share of a chunk: thread t stages G for (row group t/64, lane t%64)
   // of the tile layout (8 values) and V row s = t of this offset group (16 values)
-  gcfloat4* U4 = gc4(I.U);
-  gcfloat4* Q4 = gc4(I.Q);
   const int rg = tid >> 6, hf = (tid >> 5) & 1;
   const float* vrow = a.Vp + (size_t)(sg * kGroup + tid) * kp;
   // two register slots: the loads of chunk q + 2 are issued while chunk q is
@@ -1017,11 +1086,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big(StageArgs a) {
   float4 cu[2][2], cq[2][2], cs[2][2], cv[2][4];  // [slot][...]
   auto coop_load = [&](int q, int sl) {
     const int cb = q >> 1, p = q & 1;
-    const size_t o = (((size_t)lt * 4 + rg) * nkb + cb) * 256 + 2 * p * 64 + lane;
-    cu[sl][0] = U4[o];
-    cu[sl][1] = U4[o + 64];
-    cq[sl][0] = Q4[o];
-    cq[sl][1] = Q4[o + 64];
+    load_uq8<UB>(I, ((size_t)lt * 4 + rg) * nkb + cb, p, lane, cu[sl], cq[sl]);
     cs[sl][0] = *gc4(I.s + cb * 32 + (2 * p) * 8 + hf * 4);
     cs[sl][1] = *gc4(I.s + cb * 32 + (2 * p + 1) * 8 + hf * 4);
     gcfloat4* vp = gc4(vrow + q * kBigChunk);
@@ -1136,8 +1201,6 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = (floatx16)(0.0f);
 
-  gcfloat4* U4 = gc4(I.U);
-  gcfloat4* Q4 = gc4(I.Q);
   const float rp = (float)(1.0 / I.st->ratio_prev);
   const int rg = tid >> 6, hf = (tid >> 5) & 1;
   // thread t stages G of (row group t/64, lane t%64) of the tile layout (16 values)
@@ -1148,12 +1211,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
   const size_t vstep = (size_t)16 * (kp / 8);
   float4 cu[4], cq[4], cv0, cv1, cv2, cv3;
   auto coop_load = [&](int cb) {
-    const size_t o = (((size_t)lt * 4 + rg) * nkb + cb) * 256 + lane;
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      cu[g] = U4[o + g * 64];
-      cq[g] = Q4[o + g * 64];
-    }
+    const size_t pidx = ((size_t)lt * 4 + rg) * nkb + cb;
+    load_uq8<2>(I, pidx, 0, lane, reinterpret_cast<float4(&)[2]>(cu[0]), reinterpret_cast<float4(&)[2]>(cq[0]));
+    load_uq8<2>(I, pidx, 1, lane, reinterpret_cast<float4(&)[2]>(cu[2]), reinterpret_cast<float4(&)[2]>(cq[2]));
     cv0 = vrow[cb * 4];
     cv1 = vrow[vstep + cb * 4];
     cv2 = vrow[2 * vstep + cb * 4];
@@ -1717,7 +1777,10 @@ static void launch_adjoint_big_gv(const StageArgs& a, int ntiles_total, int mode
   const dim3 g(((ntiles_total + 7) / 8) * 8 * a.nsg), b(kThreads);
   if (mode == kFP32) {
     const int lds = std::max(2 * (128 + 256) * kBigPad, 128 * (128 + 4));
-    hipLaunchKernelGGL(k_adjoint_big<GV>, g, b, lds * 4, st, a);
+    if (a.u16)
+      hipLaunchKernelGGL((k_adjoint_big<GV, 2>), g, b, lds * 4, st, a);
+    else
+      hipLaunchKernelGGL((k_adjoint_big<GV, 4>), g, b, lds * 4, st, a);
   } else {
     const int lds = kBigLpStage + a.kp;
     if (mode == kBF16) hipLaunchKernelGGL((k_adjoint_big_lp<kBF16, GV>), g, b, lds * 4, st, a);
@@ -1736,11 +1799,13 @@ template <int GV>
 static void launch_adjoint_gv(const StageArgs& a, int ntiles_total, int lds_floats, int mode, hipStream_t st) {
   const dim3 g(((ntiles_total + 7) / 8) * 8 * a.nsg), b(kThreads);
   if (mode == kBF16)
-    hipLaunchKernelGGL((k_adjoint<kBF16, GV>), g, b, lds_floats * 4, st, a);
+    hipLaunchKernelGGL((k_adjoint<kBF16, GV, 2>), g, b, lds_floats * 4, st, a);
   else if (mode == kFP16)
-    hipLaunchKernelGGL((k_adjoint<kFP16, GV>), g, b, lds_floats * 4, st, a);
+    hipLaunchKernelGGL((k_adjoint<kFP16, GV, 2>), g, b, lds_floats * 4, st, a);
+  else if (a.u16)
+    hipLaunchKernelGGL((k_adjoint<kFP32, GV, 2>), g, b, lds_floats * 4, st, a);
   else
-    hipLaunchKernelGGL((k_adjoint<kFP32, GV>), g, b, lds_floats * 4, st, a);
+    hipLaunchKernelGGL((k_adjoint<kFP32, GV, 4>), g, b, lds_floats * 4, st, a);
 }
 
 void launch_adjoint(const StageArgs& a, int ntiles_total, int lds_floats, int mode, int gv, hipStream_t st) {
@@ -1759,16 +1824,18 @@ void launch_forward(const StageArgs& a, int ntiles_total, int lds_floats, int mo
   const size_t lds = (size_t)lds_floats * 4;
   if (mode == kBF16) {
     if (rb == 4)
-      hipLaunchKernelGGL((k_forward<kBF16, 4>), g, b, lds, st, a);
+      hipLaunchKernelGGL((k_forward<kBF16, 4, 2>), g, b, lds, st, a);
     else
-      hipLaunchKernelGGL((k_forward<kBF16, 2>), g, b, lds, st, a);
+      hipLaunchKernelGGL((k_forward<kBF16, 2, 2>), g, b, lds, st, a);
   } else if (mode == kFP16) {
     if (rb == 4)
-      hipLaunchKernelGGL((k_forward<kFP16, 4>), g, b, lds, st, a);
+      hipLaunchKernelGGL((k_forward<kFP16, 4, 2>), g, b, lds, st, a);
     else
-      hipLaunchKernelGGL((k_forward<kFP16, 2>), g, b, lds, st, a);
+      hipLaunchKernelGGL((k_forward<kFP16, 2, 2>), g, b, lds, st, a);
+  } else if (a.u16) {
+    hipLaunchKernelGGL((k_forward<kFP32, 2, 2>), g, b, lds, st, a);
   } else {
-    hipLaunchKernelGGL((k_forward<kFP32, 2>), g, b, lds, st, a);
+    hipLaunchKernelGGL((k_forward<kFP32, 2, 4>), g, b, lds, st, a);
   }
 }
 

@@ -321,7 +321,7 @@ static int padded_k(int k) { return k <= kGroup ? (k + 63) / 64 * 64 : (k + kGro
 static size_t member_bytes(const Plan& p, int kp, int nsg, int ncg, int prec) {
   size_t b = 0;
   const size_t st = (size_t)p.ntiles * p.bm * kp;
-  b += 2 * align256(st * 4);                                // U, Q
+  b += align256(st * 4) + align256(st * (prec != kFP32 ? 2 : 4));  // W; U (BF16 in the reduced precisions)
   b += align256((size_t)p.ntiles * nsg * p.E123 * 4);        // part
   b += 2 * align256((size_t)p.ntiles * kp * 4);              // qpart, wpart
   b += align256((size_t)p.ntiles * ncg * 4);                 // rpart
@@ -473,8 +473,8 @@ struct Group {
     d.mask = mb->mask;
     d.L = mb->Lout;
     const size_t stf = (size_t)p.ntiles * p.bm * kp;
-    d.U = (float*)take(stf * 4);
-    d.Q = (float*)take(stf * 4);
+    d.W = (float*)take(stf * 4);
+    d.U = take(stf * (prec != kFP32 ? 2 : 4));
     d.part = (float*)take((size_t)p.ntiles * nsg * p.E123 * 4);
     d.qpart = (float*)take((size_t)p.ntiles * kp * 4);
     d.wpart = (float*)take((size_t)p.ntiles * kp * 4);
@@ -534,6 +534,10 @@ struct Group {
     // two gathers; every plan's box fits both)
     if (const char* e = getenv("ICNNM_GATHER"))
       if (strcmp(e, "generic") == 0) gv = 0;
+    // ICNNM_LP_RB=2 keeps 64-row units in the reduced-precision forward (compares the
+    // two unit shapes; identical results)
+    if (const char* e = getenv("ICNNM_LP_RB"))
+      if (atoi(e) == 2) lp_rb = 2;
     ntiles_total = (int)tl.size();
     nlblk_total = (int)lb.size();
     nslice_total = (int)sl.size();
@@ -570,6 +574,7 @@ struct Group {
     a.kp = kp;
     a.k = k;
     a.kt = kt;
+    a.u16 = prec != kFP32 ? 1 : 0;
     a.nsg = nsg;
     a.ncg = ncg;
     a.ntiles = ntiles_total;

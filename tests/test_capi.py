@@ -92,9 +92,11 @@ def test_plan_of_a_video_tensor():
     assert tuple(-(-m // t) for m, t in zip((64, 64, 16), b)) == pl["tiles_per_dim"]
     assert pl["ntiles"] * math.prod(b) >= 64 * 64 * 16
     assert pl["state_bytes"] >= 2 * 64 * 64 * 16 * 256 * 4
-    # the reduced precisions add two m-float arrays (running adjoint and delta of L)
+    # the reduced precisions keep the multiplier U in BF16 (two bytes per state entry
+    # fewer) and add two m-float arrays (running adjoint and delta of L)
     lo = icnnm.plan((64, 64, 16), (8, 8, 4), precision="bf16")
-    assert lo["state_bytes"] >= pl["state_bytes"] + 2 * 64 * 64 * 16 * 4
+    m, kp = 64 * 64 * 16, 256
+    assert lo["state_bytes"] == pl["state_bytes"] - 2 * m * kp + 2 * m * 4
 
 
 def _gather_codes_fit(pl, dims, kdims):

@@ -23,7 +23,11 @@ def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).cuda()
 
 
-@pytest.mark.parametrize("prec,tol_oracle,tol_alone", [("fp32", 1e-5, 1e-6), ("bf16", 1e-3, 1e-5)])
+# Solved alone, an instance gets the cost model's own tile box, in the batch the box of
+# the launch's shared kernel variants: the same iteration with another summation order,
+# so the two agree to FP32 rounding accumulated over 200 iterations (1e-5, the FP32
+# parity bar), not bit for bit.
+@pytest.mark.parametrize("prec,tol_oracle,tol_alone", [("fp32", 1e-5, 1e-5), ("bf16", 1e-3, 1e-4)])
 def test_full_batch(lib, prec, tol_oracle, tol_alone):
     meta = json.load(open(os.path.join(GOLD, "batch_meta.json")))
     wl = inputs.batch_uneven(b_refs=0)

@@ -72,11 +72,23 @@ def test_reduced_precision_penalized_mode(lib, prec, lam):
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 def test_refresh_every_iteration_is_fp32(lib, prec):
+    # refresh_every = 1: every contraction runs in FP32; the reduced-precision forms
+    # still keep the multiplier U in BF16, so the result matches the FP32 solve to that
+    # storage's rounding (far inside the reduced-precision bar) and the oracle likewise,
+    # and is closer to both than the delta contractions get
     prob, V32 = _case((16, 16, 8), (4, 4, 4), 0.4, 4)
     L1, _ = lib.solve(_dev(prob.M), _dev(prob.mask), _dev(V32), prob.kdims, max_iter=30, precision=prec,
                       refresh_every=1)
     L0, _ = lib.solve(_dev(prob.M), _dev(prob.mask), _dev(V32), prob.kdims, max_iter=30)
-    assert np.array_equal(L1.cpu().numpy(), L0.cpu().numpy())
+    L10, _ = lib.solve(_dev(prob.M), _dev(prob.mask), _dev(V32), prob.kdims, max_iter=30, precision=prec)
+    L0 = L0.cpu().numpy().astype(np.float64)
+    d1 = _rel(L1.cpu().numpy(), L0)
+    d10 = _rel(L10.cpu().numpy(), L0)
+    print(f"[gpu] {prec}: refresh every iteration {d1:.2e}, every 10 {d10:.2e} from the FP32 solve", flush=True)
+    assert d1 <= 1e-4
+    assert d1 < d10
+    Lo, _ = O.solve(prob.M, prob.mask, V32.astype(np.float64), prob.kdims, 30)
+    assert _rel(L1.cpu().numpy(), Lo) <= 1e-4
 
 
 def test_refresh_improves_accuracy(lib):

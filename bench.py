@@ -132,7 +132,7 @@ def _calibrate_copy():
 def _state_bytes(precision, m, kp):
     """Algorithmic state bytes per launch of the forward (reads and writes W and the
     multiplier U) and of the adjoint (reads them) over m x kp state entries: W is FP32;
-    U is FP32 in the FP32 form and BF16 in the reduced-precision forms."""
+    U is FP32 in the FP32 form and 16 bits (FP16 of theta U) in the reduced-precision forms."""
     per = 4.0 + (4.0 if precision == "fp32" else 2.0)
     return {"forward": 2.0 * per * m * kp, "adjoint": per * m * kp}
 

@@ -10,7 +10,7 @@
 // 4g..4g+3) of lane l at position g * 64 + l. A lane reads and writes its 16
 // values as four 16-byte accesses, each of which is one contiguous kilobyte over
 // the wavefront, and the adjoint consumes them directly as its B operand without
-// a transpose. In the reduced-precision forms U is BF16 (see u16_unpack).
+// a transpose. In the reduced-precision forms U is kept in 16 bits (u16_unpack).
 //
 // Accumulator layout of v_mfma_f32_32x32x2_f32 for D = A(32 x 2) B(2 x 32):
 //   lane l, register v holds D[(v/4)*8 + (l/32)*4 + v%4][l%32];
@@ -248,37 +248,48 @@ __device__ __forceinline__ float half_sum16(float (&v)[16], int lane, int& vi) {
   return v[0];
 }
 
-// 16-bit storage of the scaled multiplier U in the reduced-precision forms (UB = 2):
-// BF16, eight values per 16-byte chunk. A piece (32 rows x 32 columns of the tile
-// layout) is 128 chunks: chunk c of lane l, values 8c..8c+7 of the lane's accumulator
-// order, at c * 64 + l, so each access is one contiguous kilobyte over the wavefront.
-__device__ __forceinline__ void u16_unpack(const uint4 h, float* v) {
+// 16-bit storage of the scaled multiplier U = Y / theta in the reduced-precision forms
+// (UB = 2): the FP16 value of the unscaled multiplier Y = theta U, whose entries stay
+// of order one (the column norms of Y are bounded near 1 by dual feasibility) while U
+// shrinks with the growing penalty; theta is the penalty the forward that wrote U
+// scaled it with (theta_next there, theta_cur for every later reader), and readers
+// multiply by the same float 1/theta. Eight values per 16-byte chunk; a piece (32
+// rows x 32 columns of the tile layout) is 128 chunks: chunk c of lane l, values
+// 8c..8c+7 of the lane's accumulator order, at c * 64 + l, so each access is one
+// contiguous kilobyte over the wavefront.
+__device__ __forceinline__ void u16_unpack(const uint4 h, float inv, float* v) {
   const uint32_t w[4] = {h.x, h.y, h.z, h.w};
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    v[2 * i] = __uint_as_float(w[i] << 16);
-    v[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+    _Float16 lo, hi;
+    const uint16_t bl = (uint16_t)(w[i] & 0xffffu), bh = (uint16_t)(w[i] >> 16);
+    __builtin_memcpy(&lo, &bl, 2);
+    __builtin_memcpy(&hi, &bh, 2);
+    v[2 * i] = (float)lo * inv;
+    v[2 * i + 1] = (float)hi * inv;
   }
 }
-__device__ __forceinline__ uint32_t u16_bits(float x) {
-  __bf16 b = (__bf16)x;  // round to nearest even
+__device__ __forceinline__ uint32_t u16_bits(float x, float scale) {
+  const _Float16 h = (_Float16)(x * scale);  // round to nearest even
   uint16_t r;
-  __builtin_memcpy(&r, &b, 2);
+  __builtin_memcpy(&r, &h, 2);
   return r;
 }
-__device__ __forceinline__ uint4 u16_pack(const float* v) {
+__device__ __forceinline__ uint4 u16_pack(const float* v, float scale) {
   uint32_t w[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) w[i] = u16_bits(v[2 * i]) | (u16_bits(v[2 * i + 1]) << 16);
+  for (int i = 0; i < 4; ++i) w[i] = u16_bits(v[2 * i], scale) | (u16_bits(v[2 * i + 1], scale) << 16);
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 // the value a stored 16-bit U reads back as
-__device__ __forceinline__ float u16_round(float x) { return __uint_as_float(u16_bits(x) << 16); }
+__device__ __forceinline__ float u16_round(float x, float scale, float inv) {
+  return (float)(_Float16)(x * scale) * inv;
+}
 
 // =====================================================================================
 // forward: W = A_k(L) V, fused with the dual update.
 // The per-instance state is W (FP32) and the scaled multiplier U = Y / theta (FP32, or
-// BF16 in the reduced-precision forms: UB = 2); Q = W - U is derived on load.
+// 16 bits in the reduced-precision forms: UB = 2, see u16_unpack); Q = W - U is derived on load.
 //   init (phase kInit): U = 0, W                             (Y^0 = 0)
 //   run  (phase kRun):  Z = s.Q_old, G = U_old + Z,
 //                       U = (G - W) theta/theta',  Q = W - U (with U as stored)
@@ -386,6 +397,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   __syncthreads();
 
   const float ratio = (float)I.st->ratio;
+  // 16-bit U: written as FP16 of theta_next U, read back (and the old U read) through
+  // the float reciprocal of the penalty it was scaled with
+  const float uscale = (float)I.st->theta, uinv = (float)(1.0 / I.st->theta);
+  const float uinv_old = (float)(1.0 / I.st->theta_cur);
   const int nkb = kp / 32;
   const int nhs = 2 * nkb;  // half-steps of 16 kernel offsets
   // a unit is RB 32-row blocks x 64 columns: RB = 2 (FP32 and reduced precision) or
@@ -609,8 +624,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
 #pragma unroll
               for (int g = 0; g < 4; ++g) uo4[g] = bu[slot][g];
             } else {
-              u16_unpack(bu[slot][0], u16v);
-              u16_unpack(bu[slot][1], u16v + 8);
+              u16_unpack(bu[slot][0], uinv_old, u16v);
+              u16_unpack(bu[slot][1], uinv_old, u16v + 8);
 #pragma unroll
               for (int g = 0; g < 4; ++g) uo4[g] = make_float4(u16v[4 * g], u16v[4 * g + 1], u16v[4 * g + 2], u16v[4 * g + 3]);
             }
@@ -657,7 +672,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
               }
               // the column norms see Q as the next iteration will derive it
               if constexpr (UB == 2) {
-                unew = u16_round(unew);
+                unew = u16_round(unew, uscale, uinv);
                 unv[4 * g + e] = unew;
               }
               const float qnew = w - unew;
@@ -671,8 +686,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
           }
           if constexpr (UB == 2) {
             uint4* Up = reinterpret_cast<uint4*>(I.U) + pidx * 128 + lane;
-            Up[0] = u16_pack(unv);
-            Up[64] = u16_pack(unv + 8);
+            Up[0] = u16_pack(unv, uscale);
+            Up[64] = u16_pack(unv + 8, uscale);
           }
           // FP32: one piece at a time (keeps the scheduler from hoisting the loads of
           // later pieces, which costs registers)
@@ -878,7 +893,7 @@ struct GatherAcc<8, CAP> {
 // float4 groups 2p and 2p + 1 of the tile layout) of W and of U for the piece at
 // piece index pidx, with Q = W - U returned in place of W.
 template <int UB>
-__device__ __forceinline__ void load_uq8(const InstDev& I, size_t pidx, int p, int lane, float4 (&u)[2],
+__device__ __forceinline__ void load_uq8(const InstDev& I, size_t pidx, int p, int lane, float uinv, float4 (&u)[2],
                                          float4 (&q)[2]) {
   gcfloat4* W4 = gc4(I.W) + pidx * 256 + 2 * p * 64 + lane;
   const float4 w0 = W4[0], w1 = W4[64];
@@ -888,7 +903,7 @@ __device__ __forceinline__ void load_uq8(const InstDev& I, size_t pidx, int p, i
     u[1] = U4[64];
   } else {
     float v[8];
-    u16_unpack(gcu4(I.U)[pidx * 128 + p * 64 + lane], v);
+    u16_unpack(gcu4(I.U)[pidx * 128 + p * 64 + lane], uinv, v);
     u[0] = make_float4(v[0], v[1], v[2], v[3]);
     u[1] = make_float4(v[4], v[5], v[6], v[7]);
   }
@@ -924,6 +939,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
   const int nkb = kp / 32;
   const int nhb = 2 * nkb;  // half column blocks of 8 MFMA k-steps
   const float* S = I.s;
+  const float uinv = (float)(1.0 / I.st->theta_cur);  // 16-bit U: see u16_unpack
   for (int rd = 0; rd < rounds; ++rd) {
     const int u = rd * 4 + wave;
     const int rc = u % nrc, sc = u / nrc;    // a round covers whole offset chunks
@@ -945,7 +961,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
     auto load = [&](int h) {
       const int cb = h >> 1, p = h & 1;
 #pragma unroll
-      for (int jb = 0; jb < 2; ++jb) load_uq8<UB>(I, row0 + (size_t)jb * nkb + cb, p, lane, fu[jb], fq[jb]);
+      for (int jb = 0; jb < 2; ++jb) load_uq8<UB>(I, row0 + (size_t)jb * nkb + cb, p, lane, uinv, fu[jb], fq[jb]);
       fs[0] = *gc4(S + cb * 32 + (2 * p) * 8 + half * 4);
       fs[1] = *gc4(S + cb * 32 + (2 * p + 1) * 8 + half * 4);
       const size_t ov = (size_t)cb * 256 + 2 * p;
@@ -994,7 +1010,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
     auto load = [&](int h) {
       const int cb = h >> 1, p = h & 1;
 #pragma unroll
-      for (int jb = 0; jb < 2; ++jb) load_uq8<UB>(I, row0 + (size_t)jb * nkb + cb, p, lane, fu[jb], fq[jb]);
+      for (int jb = 0; jb < 2; ++jb) load_uq8<UB>(I, row0 + (size_t)jb * nkb + cb, p, lane, uinv, fu[jb], fq[jb]);
       fs[0] = *gc4(S + cb * 32 + (2 * p) * 8 + half * 4);
       fs[1] = *gc4(S + cb * 32 + (2 * p + 1) * 8 + half * 4);
       fv0 = va0[(size_t)h * 64];
@@ -1080,13 +1096,14 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big(StageArgs a) {
   // cooperative share of a chunk: thread t stages G for (row group t/64, lane t%64)
   // of the tile layout (8 values) and V row s = t of this offset group (16 values)
   const int rg = tid >> 6, hf = (tid >> 5) & 1;
+  const float uinv = (float)(1.0 / I.st->theta_cur);  // 16-bit U: see u16_unpack
   const float* vrow = a.Vp + (size_t)(sg * kGroup + tid) * kp;
   // two register slots: the loads of chunk q + 2 are issued while chunk q is
   // contracted, so each chunk's global loads have two contraction phases to land
   float4 cu[2][2], cq[2][2], cs[2][2], cv[2][4];  // [slot][...]
   auto coop_load = [&](int q, int sl) {
     const int cb = q >> 1, p = q & 1;
-    load_uq8<UB>(I, ((size_t)lt * 4 + rg) * nkb + cb, p, lane, cu[sl], cq[sl]);
+    load_uq8<UB>(I, ((size_t)lt * 4 + rg) * nkb + cb, p, lane, uinv, cu[sl], cq[sl]);
     cs[sl][0] = *gc4(I.s + cb * 32 + (2 * p) * 8 + hf * 4);
     cs[sl][1] = *gc4(I.s + cb * 32 + (2 * p + 1) * 8 + hf * 4);
     gcfloat4* vp = gc4(vrow + q * kBigChunk);
@@ -1202,6 +1219,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
     for (int j = 0; j < 2; ++j) acc[i][j] = (floatx16)(0.0f);
 
   const float rp = (float)(1.0 / I.st->ratio_prev);
+  const float uinv = (float)(1.0 / I.st->theta_cur);  // 16-bit U: see u16_unpack
   const int rg = tid >> 6, hf = (tid >> 5) & 1;
   // thread t stages G of (row group t/64, lane t%64) of the tile layout (16 values)
   // and a quarter (16 bytes) of four V rows of this offset group: instruction i of
@@ -1212,8 +1230,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
   float4 cu[4], cq[4], cv0, cv1, cv2, cv3;
   auto coop_load = [&](int cb) {
     const size_t pidx = ((size_t)lt * 4 + rg) * nkb + cb;
-    load_uq8<2>(I, pidx, 0, lane, reinterpret_cast<float4(&)[2]>(cu[0]), reinterpret_cast<float4(&)[2]>(cq[0]));
-    load_uq8<2>(I, pidx, 1, lane, reinterpret_cast<float4(&)[2]>(cu[2]), reinterpret_cast<float4(&)[2]>(cq[2]));
+    load_uq8<2>(I, pidx, 0, lane, uinv, reinterpret_cast<float4(&)[2]>(cu[0]), reinterpret_cast<float4(&)[2]>(cq[0]));
+    load_uq8<2>(I, pidx, 1, lane, uinv, reinterpret_cast<float4(&)[2]>(cu[2]), reinterpret_cast<float4(&)[2]>(cq[2]));
     cv0 = vrow[cb * 4];
     cv1 = vrow[vstep + cb * 4];
     cv2 = vrow[2 * vstep + cb * 4];

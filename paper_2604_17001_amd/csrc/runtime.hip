@@ -321,7 +321,7 @@ static int padded_k(int k) { return k <= kGroup ? (k + 63) / 64 * 64 : (k + kGro
 static size_t member_bytes(const Plan& p, int kp, int nsg, int ncg, int prec) {
   size_t b = 0;
   const size_t st = (size_t)p.ntiles * p.bm * kp;
-  b += align256(st * 4) + align256(st * (prec != kFP32 ? 2 : 4));  // W; U (BF16 in the reduced precisions)
+  b += align256(st * 4) + align256(st * (prec != kFP32 ? 2 : 4));  // W; U (16 bits in the reduced precisions)
   b += align256((size_t)p.ntiles * nsg * p.E123 * 4);        // part
   b += 2 * align256((size_t)p.ntiles * kp * 4);              // qpart, wpart
   b += align256((size_t)p.ntiles * ncg * 4);                 // rpart
@@ -1763,15 +1763,20 @@ static void serve_loop(icnnm_ctx* c) {
       ServeGroup& sg = kv.second;
       const double share = sg.work > 0.0 ? wmax / sg.work : 1.0;
       const int rounds = (int)std::min<double>(kServeMaxRounds, kServeRounds * std::max(1.0, std::floor(share)));
+      // per chunk of kServeRounds rounds: only FP32, only the reduced precision, or
+      // both (a chunk is uniform, so a group keeps at most three cached graphs, which
+      // matters because membership changes drop them)
       std::vector<int> kinds(rounds, kFP32);
       if (sg.g->prec != kFP32) {
-        for (int r = 0; r < rounds; ++r) {
+        for (int r0 = 0; r0 < rounds; r0 += kServeRounds) {
           bool f32 = false, lo = false;
-          for (auto& mb : sg.active) {
-            const int kd = round_kind(mb->round + r, sg.g->prec, mb->params.max_iter, mb->params.refresh_every);
-            (kd == kFP32 ? f32 : lo) = true;
-          }
-          kinds[r] = f32 && lo ? -1 : (f32 ? (int)kFP32 : sg.g->prec);
+          for (int r = r0; r < std::min(rounds, r0 + kServeRounds); ++r)
+            for (auto& mb : sg.active) {
+              const int kd = round_kind(mb->round + r, sg.g->prec, mb->params.max_iter, mb->params.refresh_every);
+              (kd == kFP32 ? f32 : lo) = true;
+            }
+          const int kd = f32 && lo ? -1 : (f32 ? (int)kFP32 : sg.g->prec);
+          for (int r = r0; r < std::min(rounds, r0 + kServeRounds); ++r) kinds[r] = kd;
         }
       }
       rcs[kv.first] = guarded(c, [&]() -> icnnm_status {

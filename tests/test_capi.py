@@ -92,7 +92,7 @@ def test_plan_of_a_video_tensor():
     assert tuple(-(-m // t) for m, t in zip((64, 64, 16), b)) == pl["tiles_per_dim"]
     assert pl["ntiles"] * math.prod(b) >= 64 * 64 * 16
     assert pl["state_bytes"] >= 2 * 64 * 64 * 16 * 256 * 4
-    # the reduced precisions keep the multiplier U in BF16 (two bytes per state entry
+    # the reduced precisions keep the multiplier U in 16 bits (two bytes per state entry
     # fewer) and add two m-float arrays (running adjoint and delta of L)
     lo = icnnm.plan((64, 64, 16), (8, 8, 4), precision="bf16")
     m, kp = 64 * 64 * 16, 256

@@ -73,7 +73,7 @@ def test_reduced_precision_penalized_mode(lib, prec, lam):
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 def test_refresh_every_iteration_is_fp32(lib, prec):
     # refresh_every = 1: every contraction runs in FP32; the reduced-precision forms
-    # still keep the multiplier U in BF16, so the result matches the FP32 solve to that
+    # still keep the multiplier U in 16 bits, so the result matches the FP32 solve to that
     # storage's rounding (far inside the reduced-precision bar) and the oracle likewise,
     # and is closer to both than the delta contractions get
     prob, V32 = _case((16, 16, 8), (4, 4, 4), 0.4, 4)

@@ -161,9 +161,11 @@ def _headline(args):
     # pre-step (not timed in the metric): V learned on the GPU from the 20 references;
     # the solves use the oracle-learned V stored with the oracle results (the same
     # float32 V on both sides, so the error is the solver's alone)
+    refs_d = [torch.from_numpy(r).to(dev) for r in wl.refs]
+    lib.learn_eigvecs(refs_d[:1], wl.kdims)   # loads the kernels
     torch.cuda.synchronize()
     t_l = time.perf_counter()
-    lib.learn_eigvecs([torch.from_numpy(r).to(dev) for r in wl.refs], wl.kdims)
+    lib.learn_eigvecs(refs_d, wl.kdims)
     torch.cuda.synchronize()
     learn_s = time.perf_counter() - t_l
     V = torch.from_numpy(np.ascontiguousarray(np.load(_gold("batch_V.npy")))).to(dev)
@@ -501,7 +503,15 @@ def main():
     M = torch.from_numpy(prob.M).to(dev)
     mask = torch.from_numpy(prob.mask).to(dev)
     refs = [torch.from_numpy(r).to(dev) for r in wl.refs]
-    V, _ = lib.learn_eigvecs(refs, kd)          # pre-step, not timed
+    # pre-step, not in the metric: V from the workload's references (FP64 Gram from
+    # circular autocorrelations and the Jacobi eigensolver, both on the GPU); the first
+    # call also loads the kernels, so the second is timed
+    lib.learn_eigvecs(refs[:1], kd)
+    torch.cuda.synchronize()
+    t_l = time.perf_counter()
+    V, _ = lib.learn_eigvecs(refs, kd)
+    torch.cuda.synchronize()
+    learn_s = time.perf_counter() - t_l
     L = torch.empty_like(M)
     kw = dict(max_iter=wl.iters, precision=args.precision)
 
@@ -588,7 +598,8 @@ def main():
                    "iters": wl.iters, "precision": args.precision, "lambda": "inf"},
         "p50_ms": round(float(np.percentile(lat_ms, 50)), 3), "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
         "iter_us": round(1e3 * dt / args.steps / wl.iters * 1e3, 2),
-        "rel_err_vs_oracle": rel_err, "iters_run": info["iters"],
+        "rel_err_vs_oracle": rel_err, "iters_run": info["iters"], "learn_s": round(learn_s, 3),
+        "learn_refs": len(refs),
         "roofline": roofline, "stages": stages, "cpu_baseline": cpu, "other_form": other,
     }
     print(json.dumps(out), flush=True)

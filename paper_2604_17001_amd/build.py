@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libicnnm.so")
-SOURCES = ["kernels.hip", "diag.hip", "runtime.hip", "eigh.cpp"]
+SOURCES = ["kernels.hip", "diag.hip", "jacobi.hip", "runtime.hip", "eigh.cpp"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -1,6 +1,6 @@
 // FP64 kernels of the diagnostics entry point (Definition 2, eq:rkL0, eq:alphaK):
 // C = V^T G V for the Gram G = A_k(L0)^T A_k(L0) of a tensor. Kept apart from the
-// solver kernels; the Gram itself comes from the learning kernels (k_autocorr,
+// solver kernels; the Gram itself comes from the learning kernels (k_autocorr_tiled,
 // k_gram_expand).
 #include "icnnm_dev.h"
 

@@ -108,7 +108,18 @@ void launch_prep_v(const float* V, int k, int kp, float* Vf, float* Va, float* V
 // adjoint tiled for large kernels (kp >= 512, 128-row tiles)
 void launch_adjoint_big(const StageArgs& a, int ntiles_total, int mode, int gv, hipStream_t st);
 void launch_check_v(const float* V, int k, float* out_maxdev, hipStream_t st);
-void launch_autocorr(const float* L, const int32_t* m, const int32_t* k, double* R,
+// Circular autocorrelation R(d) += sum_x L[x] L[x + d] over the lag box |d_j| < k_j
+// (the Gram of A_k(L) in lag form), tiled: tiles of L with their halo in LDS, partial
+// sums per block in `part` (autocorr_part_doubles(k) doubles), then a fixed-order sum
+constexpr int kAcBlocks = 256;         // blocks of the tiled pass (each loops over tiles)
+constexpr int kAcHaloFloats = 38912;   // LDS budget of a tile's halo box (152 KB)
+struct AcGeom {
+  int m[3], k[3], t[3], h[3], nt[3];
+  int ntiles, nlags;
+};
+AcGeom autocorr_geometry(const int32_t* m, const int32_t* k);
+size_t autocorr_part_doubles(const int32_t* k);
+void launch_autocorr(const float* L, const int32_t* m, const int32_t* k, double* R, double* part,
                      hipStream_t st);
 void launch_gram_expand(const double* R, const int32_t* k, double* G, hipStream_t st);
 // FP64 products for the diagnostics: C = op(A) B for n x n row-major matrices
@@ -117,6 +128,14 @@ void launch_gemm_f64(const double* A, int trans_a, const double* B, double* C, i
 void launch_f32_to_f64(const float* src, double* dst, int64_t n, hipStream_t st);
 void launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t st);
 void launch_fill_f32(float* dst, float v, int64_t n, hipStream_t st);
+// parallel cyclic Jacobi eigensolver (jacobi.hip), order n even: A <- G padded, V <- I;
+// one round A -> B, V -> W (rot: 3 n / 2 doubles of scratch for the round's
+// rotations); off-diagonal and total sums of squares of A into out[2] (part: 512
+// doubles of scratch)
+void launch_jacobi_init(const double* G, int k, double* A, double* V, int n, hipStream_t st);
+void launch_jacobi_round(const double* A, double* B, const double* V, double* W, int n, double* rot,
+                         hipStream_t st);
+void launch_jacobi_offnorm(const double* A, int n, double* part, double* out, hipStream_t st);
 // V (kt x kt, kernel dims kd) -> the k x k bank of the padded kernel dims kdp (only the
 // innermost extent differs): rows of padded offsets and columns past kt are zero
 void launch_pad_v(const float* V, const int* kd, const int* kdp, float* out, hipStream_t st);

@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <type_traits>
+#include <vector>
 
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
@@ -1713,35 +1714,76 @@ __global__ void k_check_v(const float* V, int k, float* out) {
 // =====================================================================================
 // Gram accumulation for learning V (Definition 3, eq:A), in FP64.
 // sum_i A_k(L)[i,s] A_k(L)[i,s'] = sum_x L[x] L[x + s - s'] = R(s - s'), the circular
-// autocorrelation at lag d = s - s' in the box [-(k-1), k-1]. One block per lag.
+// autocorrelation at lag d = s - s' in the box [-(k-1), k-1]. A block stages a tile of
+// L with its circular halo (the tile extended by k - 1 on both sides) in LDS and every
+// thread accumulates kAcLpt lags over the tile's positions (products of FP32 values are
+// exact in FP64); blocks loop over tiles, so each leaves one partial per lag, and a
+// second kernel sums the partials of all blocks in a fixed order: deterministic.
 // =====================================================================================
-__global__ __launch_bounds__(kThreads) void k_autocorr(const float* L, int m0, int m1, int m2, int k0,
-                                                        int k1, int k2, double* R) {
+constexpr int kAcLpt = 16;
+
+__global__ __launch_bounds__(kThreads) void k_autocorr_tiled(const float* L, AcGeom g, double* part) {
+  extern __shared__ float halo[];
+  const int k0 = g.k[0], k1 = g.k[1], k2 = g.k[2];
   const int D1 = 2 * k1 - 1, D2 = 2 * k2 - 1;
-  const int di = blockIdx.x;
-  const int d2 = di % D2 - (k2 - 1);
-  const int d1 = (di / D2) % D1 - (k1 - 1);
-  const int d0 = di / (D1 * D2) - (k0 - 1);
-  double acc = 0.0;
-  const int rows = m0 * m1;
-  for (int row = threadIdx.x / 64; row < rows; row += kThreads / 64) {
-    const int x0 = row / m1, x1 = row % m1;
-    const int y0 = (x0 + d0 + m0) % m0, y1 = (x1 + d1 + m1) % m1;
-    const float* a = L + ((int64_t)x0 * m1 + x1) * m2;
-    const float* b = L + ((int64_t)y0 * m1 + y1) * m2;
-    for (int x2 = threadIdx.x & 63; x2 < m2; x2 += 64) {
-      int y2 = x2 + d2;
-      y2 += (y2 < 0) ? m2 : 0;
-      y2 -= (y2 >= m2) ? m2 : 0;
-      acc += (double)a[x2] * (double)b[y2];
-    }
-  }
-  __shared__ double red[kThreads / 64];
+  const int h1 = g.h[1], h2 = g.h[2], hsz = g.h[0] * h1 * h2;
+  const int lag0 = blockIdx.y * kThreads * kAcLpt;
+  int off[kAcLpt];
+  double acc[kAcLpt];
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) R[di] += red[0] + red[1] + red[2] + red[3];
+  for (int i = 0; i < kAcLpt; ++i) {
+    // lags past the last one read lag 0 (an in-box address) and are never stored, which
+    // keeps the inner loop free of branches
+    const int l = min(lag0 + (int)threadIdx.x + i * kThreads, g.nlags - 1);
+    const int d2 = l % D2 - (k2 - 1), d1 = (l / D2) % D1 - (k1 - 1), d0 = l / (D1 * D2) - (k0 - 1);
+    off[i] = (d0 * h1 + d1) * h2 + d2;
+    acc[i] = 0.0;
+  }
+  const int nown = min(kAcLpt, max(0, (g.nlags - lag0 - (int)threadIdx.x + kThreads - 1) / kThreads));
+  const int h0 = g.h[0];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int tile = blockIdx.x; tile < g.ntiles; tile += gridDim.x) {
+    const int n2 = tile % g.nt[2], r = tile / g.nt[2];
+    const int n1 = r % g.nt[1], n0 = r / g.nt[1];
+    const int o0 = n0 * g.t[0], o1 = n1 * g.t[1], o2 = n2 * g.t[2];
+    __syncthreads();  // the previous tile's reads are done
+    // one halo line (i0, i1) per wavefront pass, its i2 over the lanes; source
+    // coordinates o - (k - 1) + i lie in (-m, 3m) (tile and kernel extents <= m), so
+    // three conditional steps wrap them
+    for (int row = wave; row < h0 * h1; row += kThreads / 64) {
+      const int i0 = row / h1, i1 = row - i0 * h1;
+      const int y0 = wrap3(o0 - (k0 - 1) + i0, g.m[0]), y1 = wrap3(o1 - (k1 - 1) + i1, g.m[1]);
+      const float* src = L + ((int64_t)y0 * g.m[1] + y1) * g.m[2];
+      float* dst = halo + (size_t)row * h2;
+      for (int i2 = lane; i2 < h2; i2 += 64) dst[i2] = src[wrap3(o2 - (k2 - 1) + i2, g.m[2])];
+    }
+    __syncthreads();
+    const int e0 = min(g.t[0], g.m[0] - o0), e1 = min(g.t[1], g.m[1] - o1), e2 = min(g.t[2], g.m[2] - o2);
+    for (int p0 = 0; p0 < e0; ++p0)
+      for (int p1 = 0; p1 < e1; ++p1) {
+        const int rowb = ((p0 + k0 - 1) * h1 + (p1 + k1 - 1)) * h2 + (k2 - 1);
+        for (int p2 = 0; p2 < e2; ++p2) {
+          const int b = rowb + p2;
+          const double lx = (double)halo[b];
+#pragma unroll
+          for (int i = 0; i < kAcLpt; ++i) acc[i] = fma(lx, (double)halo[b + off[i]], acc[i]);
+        }
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < kAcLpt; ++i) {
+    const int l = lag0 + threadIdx.x + i * kThreads;
+    if (i < nown) part[(size_t)blockIdx.x * g.nlags + l] = acc[i];
+  }
+}
+
+// R[l] += sum over the nblk partials of lag l, in block order
+__global__ void k_autocorr_reduce(const double* part, int nblk, int nlags, double* R) {
+  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < nlags; l += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * nlags + l];
+    R[l] += s;
+  }
 }
 
 __global__ void k_gram_expand(const double* R, int k0, int k1, int k2, double* G) {
@@ -1869,9 +1911,59 @@ void launch_check_v(const float* V, int k, float* out, hipStream_t st) {
   hipLaunchKernelGGL(k_check_v, dim3(grid_for((int64_t)k * k, 1024)), dim3(kThreads), 0, st, V, k, out);
 }
 
-void launch_autocorr(const float* L, const int32_t* m, const int32_t* k, double* R, hipStream_t st) {
-  const int nd = (2 * k[0] - 1) * (2 * k[1] - 1) * (2 * k[2] - 1);
-  hipLaunchKernelGGL(k_autocorr, dim3(nd), dim3(kThreads), 0, st, L, m[0], m[1], m[2], k[0], k[1], k[2], R);
+AcGeom autocorr_geometry(const int32_t* m, const int32_t* k) {
+  // the tile box with the most positions per staged halo value that fits the LDS
+  // budget (t_d powers of two or the whole dimension)
+  AcGeom g{};
+  for (int d = 0; d < 3; ++d) {
+    g.m[d] = m[d];
+    g.k[d] = k[d];
+  }
+  g.nlags = (2 * k[0] - 1) * (2 * k[1] - 1) * (2 * k[2] - 1);
+  auto cands = [](int md) {
+    std::vector<int> c;
+    for (int t = 1; t < md && t <= 4096; t <<= 1) c.push_back(t);
+    c.push_back(md);
+    return c;
+  };
+  double best = -1.0;
+  for (int t0 : cands(m[0]))
+    for (int t1 : cands(m[1]))
+      for (int t2 : cands(m[2])) {
+        const int64_t h = (int64_t)(t0 + 2 * k[0] - 2) * (t1 + 2 * k[1] - 2) * (t2 + 2 * k[2] - 2);
+        const int64_t pos = (int64_t)t0 * t1 * t2;
+        if (h > kAcHaloFloats || pos > (1 << 16)) continue;
+        const double score = (double)pos / (double)h + 1e-9 * (double)pos;
+        if (score > best) {
+          best = score;
+          g.t[0] = t0;
+          g.t[1] = t1;
+          g.t[2] = t2;
+        }
+      }
+  g.ntiles = 1;
+  for (int d = 0; d < 3; ++d) {
+    g.h[d] = g.t[d] + 2 * k[d] - 2;
+    g.nt[d] = (m[d] + g.t[d] - 1) / g.t[d];
+    g.ntiles *= g.nt[d];
+  }
+  return g;
+}
+
+size_t autocorr_part_doubles(const int32_t* k) {
+  return (size_t)kAcBlocks * (2 * k[0] - 1) * (2 * k[1] - 1) * (2 * k[2] - 1);
+}
+
+void launch_autocorr(const float* L, const int32_t* m, const int32_t* k, double* R, double* part, hipStream_t st) {
+  // the smallest tile's halo is the lag box, prod(2 k_d - 1) < 8 prod(k_d) <= 32768
+  // floats, so a tile box always fits
+  const AcGeom g = autocorr_geometry(m, k);
+  const int nchunks = (g.nlags + kThreads * kAcLpt - 1) / (kThreads * kAcLpt);
+  const int nblk = std::min(kAcBlocks, g.ntiles);
+  const size_t lds = (size_t)g.h[0] * g.h[1] * g.h[2] * 4;
+  hipLaunchKernelGGL(k_autocorr_tiled, dim3(nblk, nchunks), dim3(kThreads), lds, st, L, g, part);
+  hipLaunchKernelGGL(k_autocorr_reduce, dim3((g.nlags + kThreads - 1) / kThreads), dim3(kThreads), 0, st, part,
+                     nblk, g.nlags, R);
 }
 
 void launch_gram_expand(const double* R, const int32_t* k, double* G, hipStream_t st) {

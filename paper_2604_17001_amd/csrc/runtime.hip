@@ -1366,6 +1366,69 @@ static icnnm_status do_solve_noalloc(icnnm_ctx* c, const icnnm_shape* shape, con
 }
 
 // ------------------------------------------------------------------------------ learning
+// Eigen-decomposition of the k x k FP64 Gram G (device) by the parallel cyclic Jacobi
+// kernels (jacobi.hip): w descending, V row-major [s][i] with column i the eigenvector
+// of w[i], its largest-magnitude entry made positive (the first of equal ones). An odd
+// k gets a zero row and column appended: that index never rotates (its off-diagonal
+// entries are zero), so its eigenvector stays the unit vector and is dropped.
+static void device_eig(Budget* bud, const double* G, int k, hipStream_t st, std::vector<double>& w,
+                       std::vector<double>& V) {
+  const int n = k + (k & 1);
+  const size_t nn = (size_t)n * n;
+  DevBuf A0, A1, V0, V1, nrm, rot;
+  A0.ensure(bud, nn * 8);
+  A1.ensure(bud, nn * 8);
+  V0.ensure(bud, nn * 8);
+  V1.ensure(bud, nn * 8);
+  nrm.ensure(bud, (2 + 512) * 8);
+  rot.ensure(bud, (size_t)3 * (n / 2 + 1) * 8);
+  launch_jacobi_init(G, k, A0.as<double>(), V0.as<double>(), n, st);
+  double *A = A0.as<double>(), *B = A1.as<double>(), *Vc = V0.as<double>(), *W = V1.as<double>();
+  bool converged = n <= 1;
+  for (int sweep = 0; sweep < 40 && !converged; ++sweep) {
+    for (int r = 0; r + 1 < n; ++r) {
+      launch_jacobi_round(A, B, Vc, W, n, rot.as<double>(), st);
+      std::swap(A, B);
+      std::swap(Vc, W);
+    }
+    HIPCK(hipGetLastError());
+    launch_jacobi_offnorm(A, n, nrm.as<double>() + 2, nrm.as<double>(), st);
+    double h[2] = {0.0, 0.0};
+    HIPCK(hipMemcpyAsync(h, nrm.p, 16, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    if (!std::isfinite(h[0]) || !std::isfinite(h[1])) throw Error(ICNNM_E_NUMERIC, "NaN or Inf in the Gram matrix");
+    converged = h[0] <= 1e-28 * h[1];  // off-diagonal Frobenius norm <= 1e-14 of the whole
+  }
+  if (!converged) throw Error(ICNNM_E_NUMERIC, "Jacobi eigensolver did not converge");
+  std::vector<double> Ah(nn), Vh(nn);
+  HIPCK(hipMemcpyAsync(Ah.data(), A, nn * 8, hipMemcpyDeviceToHost, st));
+  HIPCK(hipMemcpyAsync(Vh.data(), Vc, nn * 8, hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  std::vector<int> cols;
+  for (int c = 0; c < n; ++c)
+    if (n == k || Vh[(size_t)k * n + c] == 0.0) cols.push_back(c);
+  if ((int)cols.size() != k) throw Error(ICNNM_E_NUMERIC, "Jacobi eigensolver lost the padding index");
+  std::stable_sort(cols.begin(), cols.end(),
+                   [&](int a, int b) { return Ah[(size_t)a * n + a] > Ah[(size_t)b * n + b]; });
+  w.assign(k, 0.0);
+  V.assign((size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i) {
+    const int c = cols[i];
+    w[i] = Ah[(size_t)c * n + c];
+    int arg = 0;
+    double best = -1.0;
+    for (int s = 0; s < k; ++s) {
+      const double v = std::fabs(Vh[(size_t)s * n + c]);
+      if (v > best) {
+        best = v;
+        arg = s;
+      }
+    }
+    const double sg = Vh[(size_t)arg * n + c] < 0 ? -1.0 : 1.0;
+    for (int s = 0; s < k; ++s) V[(size_t)s * k + i] = sg * Vh[(size_t)s * n + c];
+  }
+}
+
 static icnnm_status do_learn(icnnm_ctx* c, const int64_t kdim_in[3], int b, const icnnm_shape* shapes,
                              const float* const* refs, float* V_out, double* eig_out, void* user_stream) {
   if (b < 1 || !shapes || !refs || !V_out || !kdim_in) throw Error(ICNNM_E_INVALID, "bad learn arguments");
@@ -1378,9 +1441,10 @@ static icnnm_status do_learn(icnnm_ctx* c, const int64_t kdim_in[3], int b, cons
   std::lock_guard<std::recursive_mutex> lock(c->mu);
   hipStream_t st = enter(c, user_stream);
   const int ndiff = (2 * kd[0] - 1) * (2 * kd[1] - 1) * (2 * kd[2] - 1);
-  DevBuf R, G;
+  DevBuf R, G, part;
   R.ensure(&c->budget, (size_t)ndiff * 8);
   G.ensure(&c->budget, (size_t)k * k * 8);
+  part.ensure(&c->budget, autocorr_part_doubles(kd) * 8);
   HIPCK(hipMemsetAsync(R.p, 0, (size_t)ndiff * 8, st));
   for (int j = 0; j < b; ++j) {
     icnnm_shape sj = shapes[j];
@@ -1389,15 +1453,12 @@ static icnnm_status do_learn(icnnm_ctx* c, const int64_t kdim_in[3], int b, cons
     int m[3], kk[3];
     normalize_shape(&sj, m, kk);
     if (!refs[j]) throw Error(ICNNM_E_INVALID, "NULL reference");
-    launch_autocorr(refs[j], m, kd, R.as<double>(), st);
+    launch_autocorr(refs[j], m, kd, R.as<double>(), part.as<double>(), st);
   }
   launch_gram_expand(R.as<double>(), kd, G.as<double>(), st);
   HIPCK(hipGetLastError());
-  std::vector<double> Gh((size_t)k * k);
-  HIPCK(hipMemcpyAsync(Gh.data(), G.p, Gh.size() * 8, hipMemcpyDeviceToHost, st));
-  HIPCK(hipStreamSynchronize(st));
   std::vector<double> w, Vd;
-  sym_eig(Gh, k, w, Vd);
+  device_eig(&c->budget, G.as<double>(), k, st, w, Vd);
   std::vector<float> Vf(Vd.size());
   for (size_t i = 0; i < Vd.size(); ++i) Vf[i] = (float)Vd[i];
   HIPCK(hipMemcpyAsync(V_out, Vf.data(), Vf.size() * 4, hipMemcpyHostToDevice, st));
@@ -1421,14 +1482,15 @@ static icnnm_status do_diag(icnnm_ctx* c, const icnnm_shape* shape, const float*
   hipStream_t st = enter(c, user_stream);
   const int ndiff = (2 * kd[0] - 1) * (2 * kd[1] - 1) * (2 * kd[2] - 1);
   const size_t kk = (size_t)k * k;
-  DevBuf R, G, Vd, T, Cm;
+  DevBuf R, G, Vd, T, Cm, part;
   R.ensure(&c->budget, (size_t)ndiff * 8);
+  part.ensure(&c->budget, autocorr_part_doubles(kd) * 8);
   G.ensure(&c->budget, kk * 8);
   Vd.ensure(&c->budget, kk * 8);
   T.ensure(&c->budget, kk * 8);
   Cm.ensure(&c->budget, kk * 8);
   HIPCK(hipMemsetAsync(R.p, 0, (size_t)ndiff * 8, st));
-  launch_autocorr(L0, m, kd, R.as<double>(), st);
+  launch_autocorr(L0, m, kd, R.as<double>(), part.as<double>(), st);
   launch_gram_expand(R.as<double>(), kd, G.as<double>(), st);
   launch_f32_to_f64(V, Vd.as<double>(), (int64_t)kk, st);
   launch_gemm_f64(G.as<double>(), 0, Vd.as<double>(), T.as<double>(), k, st);   // T = G V

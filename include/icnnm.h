@@ -109,6 +109,10 @@ typedef struct {
   double t_device_s; /* wall time from first device work to completion */
   int32_t tile[3];   /* tile box b_1..b_3 the solve ran with (order-3 form; from the
                         cost-model planner, or measured with ICNNM_AUTOTUNE=1) */
+  int32_t split;     /* 1: the contractions ran in their split form (an instance solved
+                        alone with fewer tiles than the chip has compute units: the
+                        kernel offsets of a work unit are shared by four wavefronts,
+                        which sum in a different order); 0 otherwise */
 } icnnm_info;
 
 /* Default parameters: lambda = +inf, theta0 auto, rho 1.1, theta_max 1e10,
@@ -145,6 +149,7 @@ typedef struct {
   int32_t ntiles;
   int32_t padded_k;         /* k rounded up to the contraction's column unit */
   int64_t state_bytes;
+  int32_t split;            /* 1: split contractions (see icnnm_info.split; joint = 0 only) */
 } icnnm_plan_info;
 icnnm_status icnnm_plan(const icnnm_shape *shape, const icnnm_params *params, int32_t joint,
                         icnnm_plan_info *out);

@@ -90,6 +90,9 @@ struct StageArgs {
   int32_t ntiles;        // entries of `tiles`
   int32_t tiles_per_slice;
   int32_t prec;
+  int32_t split;         // split contractions: 64-column (offset) groups, the kernel
+                         // offsets (eigendirections) of a unit shared by the four
+                         // wavefronts; then ncg = nsg = kp / 64
 };
 
 // Launchers (defined in kernels.hip). All take the stream to launch on.

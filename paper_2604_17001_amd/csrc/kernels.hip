@@ -296,11 +296,16 @@ __device__ __forceinline__ float u16_round(float x, float scale, float inv) {
 //                       U = (G - W) theta/theta',  Q = W - U (with U as stored)
 // and per-tile partial sums of Q^2, W^2 (per column) and (Z - W)^2.
 // grid = (tiles, kp / 256 column groups); each wave takes (64 rows x 64 columns) units.
+// Split form (KS, for launches with few tiles): column groups of 64, and the four
+// wavefronts of a workgroup share each unit, every one contracting a quarter of the
+// kernel offsets; the partial sums meet in LDS (fixed order) and each wavefront runs
+// the epilogue of one 32 x 32 piece. Four times the workgroups for the same work.
 // =====================================================================================
-template <int MODE, int RB, int UB>
+template <int MODE, int RB, int UB, bool KS>
 __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   static_assert(RB == 2 || (RB == 4 && MODE != kFP32), "FP32 units have two row blocks");
   static_assert(UB == 4 || UB == 2, "U is stored in 32 or 16 bits");
+  static_assert(!KS || RB == 2, "the split form has 64-row units");
   extern __shared__ float smem[];
   const int2 tt = a.tiles[blockIdx.x];
   const InstDev& I = a.inst[tt.x];
@@ -313,7 +318,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   const bool init = phase == kInit;
   const int kp = a.kp, k = a.k;
   const int cg = blockIdx.y;
-  const int CG = kp < kGroup ? kp : kGroup;
+  const int CG = KS ? kColUnit : (kp < kGroup ? kp : kGroup);
   const int lt = tt.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5;
 
@@ -332,9 +337,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   float* halo = smem;
   int* offs2 = reinterpret_cast<int*>(smem + halo_floats);
   const int noffs = MODE == kFP32 ? kp : kp / 4;
-  float* colq = reinterpret_cast<float*>(offs2 + noffs);  // [nrc][CG]
-  float* colw = colq + nrc * CG;                          // [nrc][CG]
-  float* rred = colw + nrc * CG;                          // [nrc * ncc]
+  // column partials per 64-row chunk (per 32-row block in the split form)
+  const int ncr = KS ? 2 * nrc : nrc;
+  float* colq = reinterpret_cast<float*>(offs2 + noffs);  // [ncr][CG]
+  float* colw = colq + ncr * CG;                          // [ncr][CG]
+  float* rred = colw + ncr * CG;                          // [nrc * ncc (* 4 split)]
+  float* kred = rred + nrc * ncc * (KS ? 4 : 1);          // split: [12][16][64] partials
 
   const HaloMap hm(I, o);
   if constexpr (MODE == kFP32) {
@@ -409,7 +417,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   // blocks, halving the L2 traffic of V)
   constexpr int kRpu = RB / 2;  // 64-row chunks per unit
   const int nun = (nrc / kRpu) * ncc;
-  for (int u = wave; u < nun; u += 4) {
+  // the kernel-offset half-steps this wavefront contracts
+  const int hs0 = KS ? wave * (nhs / 4) : 0, hs1 = KS ? hs0 + nhs / 4 : nhs;
+  for (int u = KS ? 0 : wave; u < nun; u += KS ? 1 : 4) {
     const int ru = u / ncc, cc = u % ncc;
     const int c0 = cg * CG + cc * kColUnit;
     bool valid[RB];
@@ -422,9 +432,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
     // the unit, so their HBM latency overlaps the contraction (the accumulators take
     // only 64 registers there). Otherwise a piece's loads are issued one or two pieces
     // ahead, overlapping the arithmetic and stores of the pieces before it.
+    // Split form: the one piece the wavefront finishes is loaded before the contraction.
     constexpr int kPieces = 2 * RB;
-    constexpr bool kEarly = MODE != kFP32 && RB == 2;
-    constexpr int kAhead = kEarly ? kPieces : (RB == 4 ? 1 : 2);  // pieces of U/Q loads in flight
+    constexpr bool kEarly = MODE != kFP32 && RB == 2 && !KS;
+    constexpr int kAhead = KS ? 1 : (kEarly ? kPieces : (RB == 4 ? 1 : 2));  // pieces of U/Q loads in flight
     float rsum[kRpu];
 #pragma unroll
     for (int r = 0; r < kRpu; ++r) rsum[r] = 0.f;
@@ -452,6 +463,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
 #pragma unroll
       for (int i = 0; i < kPieces; ++i) load_piece(i, i);
     }
+    if (KS && !init) load_piece(wave, 0);
 
     floatx16 acc[2][RB];
 #pragma unroll
@@ -505,24 +517,25 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
         acc[1][1] = mfma32(a1[jj], b[1][jj], acc[1][1]);
       }
     };
-    // nhs is even (kp is a multiple of 64); fetches past the last half-step are
-    // clamped to it, which keeps the body branch-free
-    fetch_t(0);
+    // the range [hs0, hs1) has an even length (kp is a multiple of 64, of 128 in the
+    // split form); fetches past its last half-step are clamped to it, which keeps the
+    // body branch-free
+    fetch_t(hs0);
     fetch_b(bv[0]);
-    fetch_v(0, va[0]);
-    fetch_t(1);
+    fetch_v(hs0, va[0]);
+    fetch_t(hs0 + 1);
     // (the scheduling barriers keep the compiler from sinking the fetches below the
     // MFMAs that do not depend on them)
-    for (int h = 0; h < nhs; h += 2) {
+    for (int h = hs0; h < hs1; h += 2) {
       fetch_v(h + 1, va[1]);
       fetch_b(bv[1]);
-      fetch_t(min(h + 2, nhs - 1));
+      fetch_t(min(h + 2, hs1 - 1));
       __builtin_amdgcn_sched_barrier(0);
       mfma_half(va[0], bv[0]);
       __builtin_amdgcn_sched_barrier(0);
-      fetch_v(min(h + 2, nhs - 1), va[0]);
+      fetch_v(min(h + 2, hs1 - 1), va[0]);
       fetch_b(bv[0]);
-      fetch_t(min(h + 3, nhs - 1));
+      fetch_t(min(h + 3, hs1 - 1));
       __builtin_amdgcn_sched_barrier(0);
       mfma_half(va[1], bv[1]);
       __builtin_amdgcn_sched_barrier(0);
@@ -538,8 +551,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
     // they are loaded kPf steps ahead into a ring of registers; the LDS reads of D run
     // one step ahead. Each step issues its MFMAs first and then refills the ring slot
     // and the halo buffer it has just consumed, so the loads land in the registers
-    // the step read (no copies, exact wait counts). nhs is a multiple of kPf (kp is a
-    // multiple of 64).
+    // the step read (no copies, exact wait counts). The range [hs0, hs1) has a multiple
+    // of kPf steps (kp is a multiple of 64, of 256 in the split form).
     constexpr int kPf = RB == 4 ? 2 : 4;  // eight MFMAs per step with four row blocks
     typedef typename LowP<MODE>::gv8 GV8;
     GV8* vf0 = reinterpret_cast<GV8*>(gc4(a.Vf_lo)) + (size_t)(c0 / 32) * nhs * 64 + lane;
@@ -556,11 +569,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
     };
 #pragma unroll
     for (int i = 0; i < kPf; ++i) {
-      ra[i][0] = vf0[(size_t)i * 64];
-      ra[i][1] = vf1[(size_t)i * 64];
+      ra[i][0] = vf0[(size_t)(hs0 + i) * 64];
+      ra[i][1] = vf1[(size_t)(hs0 + i) * 64];
     }
-    load_d(0, 0);
-    for (int kb = 0; kb < nhs; kb += kPf) {
+    load_d(hs0, 0);
+    for (int kb = hs0; kb < hs1; kb += kPf) {
 #pragma unroll
       for (int i = 0; i < kPf; ++i) {
         const int kk = kb + i, cur = i & 1;
@@ -573,7 +586,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
             bv[ib][4 + j] = bn[cur][ib][1][j];
           }
         // the halo reads of the next step go to the other parity buffer
-        load_d(min(kk + 1, nhs - 1), cur ^ 1);
+        load_d(min(kk + 1, hs1 - 1), cur ^ 1);
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
@@ -581,11 +594,41 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
         __builtin_amdgcn_sched_barrier(0);
         // unconditional (clamped) refill keeps the body branch-free; the last steps
         // reload the final fragments harmlessly
-        const int kn = min(kk + kPf, nhs - 1);
+        const int kn = min(kk + kPf, hs1 - 1);
         ra[i][0] = vf0[(size_t)kn * 64];
         ra[i][1] = vf1[(size_t)kn * 64];
       }
     }
+    }
+
+    if constexpr (KS) {
+      // the partial sums of the pieces the wavefront does not finish go to LDS (slot
+      // 3 pc + rank of the wavefront among the other three); the owner of piece pc
+      // (wavefront pc) adds the four partials in wavefront order
+#pragma unroll
+      for (int pc = 0; pc < kPieces; ++pc)
+        if (pc != wave) {
+          float* d = kred + (3 * pc + (wave < pc ? wave : wave - 1)) * 1024 + lane;
+#pragma unroll
+          for (int v = 0; v < 16; ++v) d[v * 64] = acc[pc / RB][pc % RB][v];
+        }
+      __syncthreads();
+#pragma unroll
+      for (int pc = 0; pc < kPieces; ++pc)
+        if (pc == wave) {
+          floatx16 sum = (floatx16)(0.0f);
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            if (w == pc) {
+              sum += acc[pc / RB][pc % RB];
+            } else {
+              const float* d = kred + (3 * pc + (w < pc ? w : w - 1)) * 1024 + lane;
+#pragma unroll
+              for (int v = 0; v < 16; ++v) sum[v] += d[v * 64];
+            }
+          }
+          acc[pc / RB][pc % RB] = sum;
+        }
     }
 
     // Two compiled forms of the same arithmetic: the first forward of a solve (U = 0,
@@ -594,12 +637,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
     // derived from them is zero as well without further masking.
     auto epilogue = [&](auto init_c) {
       constexpr bool kFirst = decltype(init_c)::value;
-      if constexpr (!kFirst && !kEarly) {
+      if constexpr (!kFirst && !kEarly && !KS) {
 #pragma unroll
         for (int i = 0; i < kAhead; ++i) load_piece(i, i);
       }
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb) {
+        if (KS && cb != wave / RB) continue;  // split form: only the wavefront's own piece
         const int cblk = c0 / 32 + cb;
         float4 s4[4];
 #pragma unroll
@@ -612,7 +656,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
         for (int v = 0; v < 16; ++v) qs[v] = ws[v] = 0.f;
 #pragma unroll
         for (int ib = 0; ib < RB; ++ib) {
-          const int pc = cb * RB + ib, slot = pc % kAhead;
+          if (KS && ib != wave % RB) continue;
+          const int pc = cb * RB + ib, slot = KS ? 0 : pc % kAhead;
           // the piece's old U, unpacked from BF16 (UB = 2; FP32 U is read in place)
           float u16v[UB == 2 ? 16 : 1];
           float4 wo4[4], uo4[4];
@@ -630,7 +675,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
 #pragma unroll
               for (int g = 0; g < 4; ++g) uo4[g] = make_float4(u16v[4 * g], u16v[4 * g + 1], u16v[4 * g + 2], u16v[4 * g + 3]);
             }
-            if (pc + kAhead < kPieces) load_piece(pc + kAhead, slot);
+            if (!KS && pc + kAhead < kPieces) load_piece(pc + kAhead, slot);
           }
           const size_t pidx = ((size_t)lt * (I.bm / 32) + ru * RB + ib) * nkb + cblk;
           gfloat4* Wp = g4(I.W) + pidx * 256 + lane;
@@ -693,13 +738,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
           // FP32: one piece at a time (keeps the scheduler from hoisting the loads of
           // later pieces, which costs registers)
           if constexpr (MODE == kFP32) __builtin_amdgcn_sched_barrier(0);
-          if (ib & 1) {  // column partials of one 64-row chunk
+          if (KS || (ib & 1)) {  // column partials of one 64-row chunk (32-row block: split)
             int vi;
             const float q = half_sum16(qs, lane, vi);
             const float w = half_sum16(ws, lane, vi);
             if ((lane & 1) == 0) {
               const int col = cc * kColUnit + cb * 32 + acc_col(vi, half);
-              const int rc = ru * kRpu + ib / 2;
+              const int rc = KS ? ru * RB + ib : ru * kRpu + ib / 2;
               colq[rc * CG + col] = q;
               colw[rc * CG + col] = w;
             }
@@ -717,13 +762,14 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
 #pragma unroll
     for (int r = 0; r < kRpu; ++r) {
       const float rs = wave_sum(rsum[r]);
-      if (lane == 0) rred[(ru * kRpu + r) * ncc + cc] = rs;
+      if (lane == 0) rred[KS ? u * 4 + wave : (ru * kRpu + r) * ncc + cc] = rs;
     }
+    if constexpr (KS) __syncthreads();  // the partial-sum slots are reused by the next unit
   }
   __syncthreads();
   for (int c = tid; c < CG; c += kThreads) {
     float q = 0.f, w = 0.f;
-    for (int rc = 0; rc < nrc; ++rc) {
+    for (int rc = 0; rc < ncr; ++rc) {
       q += colq[rc * CG + c];
       w += colw[rc * CG + c];
     }
@@ -732,7 +778,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   }
   if (tid == 0) {
     float r = 0.f;
-    for (int u = 0; u < nrc * ncc; ++u) r += rred[u];
+    for (int u = 0; u < nrc * ncc * (KS ? 4 : 1); ++u) r += rred[u];
     I.rpart[(size_t)lt * a.ncg + cg] = r;
   }
 }
@@ -912,7 +958,11 @@ __device__ __forceinline__ void load_uq8(const InstDev& I, size_t pidx, int p, i
   q[1] = make_float4(w1.x - u[1].x, w1.y - u[1].y, w1.z - u[1].z, w1.w - u[1].w);
 }
 
-template <int MODE, int GV, int UB>
+// Split form (KS, for launches with few tiles): offset groups of 64, one round, and
+// the four wavefronts share each unit (64 rows x 64 offsets), every one contracting a
+// quarter of the eigendirections; the partial sums meet in LDS in a fixed order and
+// each wavefront stages one 32 x 32 piece of H^T.
+template <int MODE, int GV, int UB, bool KS>
 __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
   extern __shared__ float smem[];
   int2 tt;
@@ -921,16 +971,17 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
   const InstDev& I = a.inst[tt.x];
   if (I.st->phase != kRun || !runs_iteration<MODE>(I, I.st)) return;
   const int kp = a.kp, k = a.k;
-  const int SGW = kp < kGroup ? kp : kGroup;
+  const int SGW = KS ? kColUnit : (kp < kGroup ? kp : kGroup);
   const int lt = tt.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5;
   const int bm = I.bm;
   const int nrc = bm / kRowUnit, nsc = SGW / kColUnit;
   const int units = nrc * nsc;
-  const int rounds = units >= 4 ? units / 4 : 1;  // four units per round (fewer when small)
+  const int rounds = (units >= 4 && !KS) ? units / 4 : 1;  // four units per round (fewer when small)
   const int spr = (SGW / rounds);             // kernel offsets per round
   const int hstride = bm + 4;                 // LDS row stride of the staged H^T
   float* Hs = smem;                           // [spr][hstride]
+  float* kred = Hs + spr * hstride;           // split: [12][16][64] partial sums
 
   // owned box positions and their valid kernel-offset ranges per dimension
   const int E123 = I.E123;
@@ -941,11 +992,14 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
   const int nhb = 2 * nkb;  // half column blocks of 8 MFMA k-steps
   const float* S = I.s;
   const float uinv = (float)(1.0 / I.st->theta_cur);  // 16-bit U: see u16_unpack
+  // the eigendirection half blocks this wavefront contracts
+  const int hb0 = KS ? wave * (nhb / 4) : 0, hb1 = KS ? hb0 + nhb / 4 : nhb;
   for (int rd = 0; rd < rounds; ++rd) {
-    const int u = rd * 4 + wave;
+    const int S0 = sg * SGW + rd * spr;      // first offset staged this round
+    for (int ui = 0; ui < (KS ? nrc : 1); ++ui) {
+    const int u = KS ? ui : rd * 4 + wave;
     const int rc = u % nrc, sc = u / nrc;    // a round covers whole offset chunks
     const int s0 = sg * SGW + sc * kColUnit;
-    const int S0 = sg * SGW + rd * spr;      // first offset staged this round
     if (u < units) {
     floatx16 acc[2][2];
 #pragma unroll
@@ -971,8 +1025,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
       fv[1][0] = va1[ov];
       fv[1][1] = va1[ov + 1];
     };
-    load(0);
-    for (int h = 0; h < nhb; ++h) {
+    load(hb0);
+    for (int h = hb0; h < hb1; ++h) {
       float g[2][8];
 #pragma unroll
       for (int jb = 0; jb < 2; ++jb) {
@@ -988,7 +1042,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
                            fv[0][1].x, fv[0][1].y, fv[0][1].z, fv[0][1].w};
       const float v1[8] = {fv[1][0].x, fv[1][0].y, fv[1][0].z, fv[1][0].w,
                            fv[1][1].x, fv[1][1].y, fv[1][1].z, fv[1][1].w};
-      if (h + 1 < nhb) load(h + 1);
+      if (h + 1 < hb1) load(h + 1);
 #pragma unroll
       for (int jj = 0; jj < 8; ++jj) {
         acc[0][0] = mfma32(v0[jj], g[0][jj], acc[0][0]);
@@ -1017,8 +1071,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
       fv0 = va0[(size_t)h * 64];
       fv1 = va1[(size_t)h * 64];
     };
-    load(0);
-    for (int h = 0; h < nhb; ++h) {
+    load(hb0);
+    for (int h = hb0; h < hb1; ++h) {
       V8 g[2];
 #pragma unroll
       for (int jb = 0; jb < 2; ++jb) {
@@ -1033,13 +1087,46 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
       V8 v0, v1;
       __builtin_memcpy(&v0, &fv0, 16);
       __builtin_memcpy(&v1, &fv1, 16);
-      if (h + 1 < nhb) load(h + 1);
+      if (h + 1 < hb1) load(h + 1);
       acc[0][0] = LowP<MODE>::mfma(v0, g[0], acc[0][0]);
       acc[0][1] = LowP<MODE>::mfma(v0, g[1], acc[0][1]);
       acc[1][0] = LowP<MODE>::mfma(v1, g[0], acc[1][0]);
       acc[1][1] = LowP<MODE>::mfma(v1, g[1], acc[1][1]);
     }
     }
+    if constexpr (KS) {
+      // partial sums of the pieces (sb, jb) = (pc / 2, pc % 2) the wavefront does not
+      // stage go to LDS; the owner (wavefront pc) adds the four in wavefront order
+#pragma unroll
+      for (int pc = 0; pc < 4; ++pc)
+        if (pc != wave) {
+          float* d = kred + (3 * pc + (wave < pc ? wave : wave - 1)) * 1024 + lane;
+#pragma unroll
+          for (int v = 0; v < 16; ++v) d[v * 64] = acc[pc / 2][pc % 2][v];
+        }
+      __syncthreads();
+#pragma unroll
+      for (int pc = 0; pc < 4; ++pc)
+        if (pc == wave) {
+          floatx16 sum = (floatx16)(0.0f);
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            if (w == pc) {
+              sum += acc[pc / 2][pc % 2];
+            } else {
+              const float* d = kred + (3 * pc + (w < pc ? w : w - 1)) * 1024 + lane;
+#pragma unroll
+              for (int v = 0; v < 16; ++v) sum[v] += d[v * 64];
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int sl = s0 + (pc / 2) * 32 + acc_col(v, half) - S0;
+            Hs[sl * hstride + rc * 64 + (pc % 2) * 32 + (lane & 31)] = sum[v];
+          }
+        }
+      __syncthreads();  // the partial-sum slots are reused by the next unit
+    } else {
     // stage H^T of this unit: Hs[s - S0][row]
 #pragma unroll
     for (int sb = 0; sb < 2; ++sb)
@@ -1050,6 +1137,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
           const int sl = s0 + sb * 32 + acc_col(v, half) - S0;
           Hs[sl * hstride + rc * 64 + jb * 32 + (lane & 31)] = acc[sb][jb][v];
         }
+    }
+    }
     }
     __syncthreads();
     gacc.round(I, Hs, hstride, S0, min(S0 + spr, k));
@@ -1310,6 +1399,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
 //        finite lambda: L = (theta T/k + lambda M)/(lambda + theta) on Omega, T/k elsewhere
 //        partial sums of ||L_new - L_old||^2
 // =====================================================================================
+template <int KG>
 __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
   const int2 lb = a.lblocks[blockIdx.x];
   const InstDev& I = a.inst[lb.x];
@@ -1350,8 +1440,10 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
     const int C1 = I.C[1], C2 = I.C[2];
     const int npair = I.C[0] * C1;
     const int gsh = I.gshift, gmask = (1 << gsh) - 1;  // entry = (tile << gsh) | position
-    constexpr int kC2 = 4, kPr = 4;  // fast path: C2 <= 4, <= 4 pairs per lane, one offset group
-    if (C2 <= kC2 && nsg == 1 && npair <= kPr * kLanesPerElem) {
+    // fast path: C2 <= 4, <= 4 pairs per lane, <= KG offset groups (1, or 4 for the
+    // split form's four per 256 offsets); same summation order as the general loop below
+    constexpr int kC2 = 4, kPr = 4, kG = KG;
+    if (C2 <= kC2 && nsg <= kG && npair <= kPr * kLanesPerElem) {
       int e2v[kC2];
 #pragma unroll
       for (int c2 = 0; c2 < kC2; ++c2) e2v[c2] = c2 < C2 ? g2[c2] : -1;
@@ -1366,7 +1458,7 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
           e1v[j] = g1[c1];
         }
       }
-      float v[kPr][kC2];
+      float v[kPr][kC2][kG];
 #pragma unroll
       for (int j = 0; j < kPr; ++j) {
         const int e0 = e0v[j], e1 = e1v[j];
@@ -1376,14 +1468,20 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
 #pragma unroll
         for (int c2 = 0; c2 < kC2; ++c2) {
           const int e2 = e2v[c2];
-          v[j][c2] = 0.f;
-          if (okp && e2 >= 0) v[j][c2] = I.part[(size_t)(tb + (e2 >> gsh)) * I.E123 + pb + (e2 & gmask)];
+          const float* pp = I.part + ((size_t)(tb + (e2 >> gsh)) * nsg) * I.E123 + pb + (e2 & gmask);
+#pragma unroll
+          for (int g = 0; g < kG; ++g) {
+            v[j][c2][g] = 0.f;
+            if (okp && e2 >= 0 && g < nsg) v[j][c2][g] = pp[(size_t)g * I.E123];
+          }
         }
       }
 #pragma unroll
       for (int j = 0; j < kPr; ++j)
 #pragma unroll
-        for (int c2 = 0; c2 < kC2; ++c2) T += v[j][c2];
+        for (int c2 = 0; c2 < kC2; ++c2)
+#pragma unroll
+          for (int g = 0; g < kG; ++g) T += v[j][c2][g];
     } else {
       for (int pr = sub; pr < npair; pr += kLanesPerElem) {
         const int c0 = pr / C1, c1 = pr - c0 * C1;
@@ -1855,48 +1953,62 @@ void launch_adjoint_big(const StageArgs& a, int ntiles_total, int mode, int gv, 
     launch_adjoint_big_gv<0>(a, ntiles_total, mode, st);
 }
 
-template <int GV>
+template <int GV, bool KS>
 static void launch_adjoint_gv(const StageArgs& a, int ntiles_total, int lds_floats, int mode, hipStream_t st) {
   const dim3 g(((ntiles_total + 7) / 8) * 8 * a.nsg), b(kThreads);
   if (mode == kBF16)
-    hipLaunchKernelGGL((k_adjoint<kBF16, GV, 2>), g, b, lds_floats * 4, st, a);
+    hipLaunchKernelGGL((k_adjoint<kBF16, GV, 2, KS>), g, b, lds_floats * 4, st, a);
   else if (mode == kFP16)
-    hipLaunchKernelGGL((k_adjoint<kFP16, GV, 2>), g, b, lds_floats * 4, st, a);
+    hipLaunchKernelGGL((k_adjoint<kFP16, GV, 2, KS>), g, b, lds_floats * 4, st, a);
   else if (a.u16)
-    hipLaunchKernelGGL((k_adjoint<kFP32, GV, 2>), g, b, lds_floats * 4, st, a);
+    hipLaunchKernelGGL((k_adjoint<kFP32, GV, 2, KS>), g, b, lds_floats * 4, st, a);
   else
-    hipLaunchKernelGGL((k_adjoint<kFP32, GV, 4>), g, b, lds_floats * 4, st, a);
+    hipLaunchKernelGGL((k_adjoint<kFP32, GV, 4, KS>), g, b, lds_floats * 4, st, a);
 }
 
 void launch_adjoint(const StageArgs& a, int ntiles_total, int lds_floats, int mode, int gv, hipStream_t st) {
   if (gv == 8)
-    launch_adjoint_gv<8>(a, ntiles_total, lds_floats, mode, st);
+    a.split ? launch_adjoint_gv<8, true>(a, ntiles_total, lds_floats, mode, st)
+            : launch_adjoint_gv<8, false>(a, ntiles_total, lds_floats, mode, st);
   else
-    launch_adjoint_gv<0>(a, ntiles_total, lds_floats, mode, st);
+    a.split ? launch_adjoint_gv<0, true>(a, ntiles_total, lds_floats, mode, st)
+            : launch_adjoint_gv<0, false>(a, ntiles_total, lds_floats, mode, st);
 }
 
 void launch_lstep(const StageArgs& a, int nlblocks_total, hipStream_t st) {
-  hipLaunchKernelGGL(k_lstep, dim3(nlblocks_total), dim3(kThreads), 0, st, a);
+  if (a.nsg == 1)
+    hipLaunchKernelGGL(k_lstep<1>, dim3(nlblocks_total), dim3(kThreads), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_lstep<4>, dim3(nlblocks_total), dim3(kThreads), 0, st, a);
 }
 
-void launch_forward(const StageArgs& a, int ntiles_total, int lds_floats, int mode, int rb, hipStream_t st) {
+template <bool KS>
+static void launch_forward_ks(const StageArgs& a, int ntiles_total, int lds_floats, int mode, int rb,
+                              hipStream_t st) {
   const dim3 g(ntiles_total, a.ncg), b(kThreads);
   const size_t lds = (size_t)lds_floats * 4;
   if (mode == kBF16) {
-    if (rb == 4)
-      hipLaunchKernelGGL((k_forward<kBF16, 4, 2>), g, b, lds, st, a);
+    if (rb == 4 && !KS)
+      hipLaunchKernelGGL((k_forward<kBF16, 4, 2, false>), g, b, lds, st, a);
     else
-      hipLaunchKernelGGL((k_forward<kBF16, 2, 2>), g, b, lds, st, a);
+      hipLaunchKernelGGL((k_forward<kBF16, 2, 2, KS>), g, b, lds, st, a);
   } else if (mode == kFP16) {
-    if (rb == 4)
-      hipLaunchKernelGGL((k_forward<kFP16, 4, 2>), g, b, lds, st, a);
+    if (rb == 4 && !KS)
+      hipLaunchKernelGGL((k_forward<kFP16, 4, 2, false>), g, b, lds, st, a);
     else
-      hipLaunchKernelGGL((k_forward<kFP16, 2, 2>), g, b, lds, st, a);
+      hipLaunchKernelGGL((k_forward<kFP16, 2, 2, KS>), g, b, lds, st, a);
   } else if (a.u16) {
-    hipLaunchKernelGGL((k_forward<kFP32, 2, 2>), g, b, lds, st, a);
+    hipLaunchKernelGGL((k_forward<kFP32, 2, 2, KS>), g, b, lds, st, a);
   } else {
-    hipLaunchKernelGGL((k_forward<kFP32, 2, 4>), g, b, lds, st, a);
+    hipLaunchKernelGGL((k_forward<kFP32, 2, 4, KS>), g, b, lds, st, a);
   }
+}
+
+void launch_forward(const StageArgs& a, int ntiles_total, int lds_floats, int mode, int rb, hipStream_t st) {
+  if (a.split)
+    launch_forward_ks<true>(a, ntiles_total, lds_floats, mode, rb, st);
+  else
+    launch_forward_ks<false>(a, ntiles_total, lds_floats, mode, rb, st);
 }
 
 void launch_prep_v(const float* V, int k, int kp, float* Vf, float* Va, float* Vp, void* Vf_lo, void* Va_lo,

@@ -113,6 +113,7 @@ struct Plan {
   int m[3], k[3], b[3], E[3], nt[3], C[3], goff[3];
   int ntiles, bm, E123, nlblk, nslice;
   int gshift;  // gather-table entries pack (tile index << gshift) | box position
+  bool split = false;  // split contractions (64-wide groups, offsets shared by the wavefronts)
   int64_t mtot;
   std::vector<int32_t> gtab;
   size_t state_floats() const;
@@ -126,12 +127,17 @@ static int pow2ceil(int v) {
   return p;
 }
 
-static int lds_forward_floats(const Plan& p, int kp) {
+// partial sums of the split contractions: 12 slots of one 32x32 accumulator piece
+constexpr int kSplitRedFloats = 12 * 16 * 64;
+
+static int lds_forward_floats(const Plan& p, int kp, bool split = false) {
   // FP32: halo + offset table; reduced precision: 4-wide expanded halo of 16-bit values
-  // (2 floats per position) + a quarter-size offset table; the larger of the two
-  const int CG = std::min(kp, kGroup);
+  // (2 floats per position) + a quarter-size offset table; the larger of the two; then
+  // the column and residual partials (and the split form's partial sums)
+  const int CG = split ? kColUnit : std::min(kp, kGroup);
   const int nrc = p.bm / kRowUnit, ncc = CG / kColUnit;
   const int h32 = ((p.E123 + 3) & ~3) + kp, hlp = 2 * p.E123 + kp / 4;
+  if (split) return std::max(h32, hlp) + 2 * (2 * nrc) * CG + 4 * nrc * ncc + kSplitRedFloats;
   return std::max(h32, hlp) + 2 * nrc * CG + nrc * ncc;
 }
 
@@ -141,8 +147,10 @@ static bool lines_gather_fits(const Plan& p) {
   return p.k[2] == 4 && p.b[2] == 8 && p.E[0] * p.E[1] <= 2 * kThreads;
 }
 
-static int lds_adjoint_floats(const Plan& p, int kp) {
-  // staged H^T of one round: (offsets per round) x (tile rows + 4)
+static int lds_adjoint_floats(const Plan& p, int kp, bool split = false) {
+  // staged H^T of one round: (offsets per round) x (tile rows + 4); the split form
+  // stages 64 offsets in one round, after its partial sums
+  if (split) return kColUnit * (p.bm + 4) + kSplitRedFloats;
   const int SGW = std::min(kp, kGroup);
   const int units = (p.bm / kRowUnit) * (SGW / kColUnit);
   const int rounds = units >= 4 ? units / 4 : 1;
@@ -295,6 +303,21 @@ static Plan plan_with_box(const int m[3], const int k[3], int kp, const int b[3]
   return make_plan(m, k, kp);
 }
 
+// Split contractions for an instance solved alone whose launches would otherwise have
+// fewer workgroups than the chip has compute units: 64-row tiles, kp a multiple of 128
+// (FP32) or 256 (BF16/FP16: their forward contracts 64 offsets per step). ICNNM_SPLIT=0
+// or 1 forces the choice where the plan admits the split form.
+constexpr int kSplitBelowWorkgroups = 256;
+
+static void decide_split(Plan& p, int kp, int prec) {
+  const int nsg = (kp + kGroup - 1) / kGroup;
+  bool fits = p.bm == kRowUnit && kp % (prec == kFP32 ? 128 : 256) == 0 &&
+              lds_forward_floats(p, kp, true) * 4 <= 150 * 1024 && lds_adjoint_floats(p, kp, true) * 4 <= 150 * 1024;
+  bool want = (int64_t)p.ntiles * nsg < kSplitBelowWorkgroups;
+  if (const char* e = getenv("ICNNM_SPLIT")) want = atoi(e) != 0;
+  p.split = fits && want;
+}
+
 // ------------------------------------------------------------------------------ group executor
 // One solve state: the device arrays of one instance.
 struct Member {
@@ -318,7 +341,12 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // workgroup group once k exceeds one group
 static int padded_k(int k) { return k <= kGroup ? (k + 63) / 64 * 64 : (k + kGroup - 1) / kGroup * kGroup; }
 
-static size_t member_bytes(const Plan& p, int kp, int nsg, int ncg, int prec) {
+// column groups of the forward and offset groups of the adjoint (halo partials per
+// tile): 256 wide, or 64 wide in the split form
+static int plan_groups(const Plan& p, int kp) { return p.split ? kp / kColUnit : (kp + kGroup - 1) / kGroup; }
+
+static size_t member_bytes(const Plan& p, int kp, int prec) {
+  const int nsg = plan_groups(p, kp), ncg = nsg;
   size_t b = 0;
   const size_t st = (size_t)p.ntiles * p.bm * kp;
   b += align256(st * 4) + align256(st * (prec != kFP32 ? 2 : 4));  // W; U (16 bits in the reduced precisions)
@@ -362,6 +390,7 @@ struct Group {
   DevBuf Vf, Va, Vp, Vlo_f, Vlo_a, Vlo_p;
   DevBuf Vpad;  // V with the zero rows and columns of padded kernel offsets
   bool big = false;  // adjoint tiled for operand reuse: kp a multiple of 256, 128-row tiles
+  bool split = false;  // split contractions: every member's plan has the split form
   std::vector<Member*> members;
   int capacity;
   DevBuf states;  // InstState[capacity]
@@ -435,7 +464,7 @@ struct Group {
   void attach(Member* mb, hipStream_t st) {
     if (free_slots.empty()) throw Error(ICNNM_E_BUDGET, "no free slot in group");
     const Plan& p = mb->plan;
-    mb->buf.ensure(budget, member_bytes(p, kp, nsg, ncg, prec));
+    mb->buf.ensure(budget, member_bytes(p, kp, prec));
     char* base = mb->buf.as<char>();
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -475,10 +504,10 @@ struct Group {
     const size_t stf = (size_t)p.ntiles * p.bm * kp;
     d.W = (float*)take(stf * 4);
     d.U = take(stf * (prec != kFP32 ? 2 : 4));
-    d.part = (float*)take((size_t)p.ntiles * nsg * p.E123 * 4);
+    d.part = (float*)take((size_t)p.ntiles * plan_groups(p, kp) * p.E123 * 4);
     d.qpart = (float*)take((size_t)p.ntiles * kp * 4);
     d.wpart = (float*)take((size_t)p.ntiles * kp * 4);
-    d.rpart = (float*)take((size_t)p.ntiles * ncg * 4);
+    d.rpart = (float*)take((size_t)p.ntiles * plan_groups(p, kp) * 4);
     d.dlpart = (double*)take((size_t)p.nlblk * 16);
     d.slice = (double*)take((size_t)(2 * kp + 3 * p.nslice) * 8);
     d.s = (float*)take((size_t)kp * 4);
@@ -518,6 +547,9 @@ struct Group {
     gv = members.empty() ? 0 : 8;
     big = kp % kGroup == 0;
     lp_rb = members.empty() ? 2 : 4;
+    split = !members.empty();
+    for (const Member* mb : members)
+      if (!mb->plan.split) split = false;
     for (size_t i = 0; i < members.size(); ++i) {
       const Member* mb = members[i];
       if (!lines_gather_fits(mb->plan)) gv = 0;
@@ -527,8 +559,8 @@ struct Group {
       for (int t = 0; t < mb->plan.ntiles; ++t) tl.push_back(make_int2((int)i, t));
       for (int t = 0; t < mb->plan.nlblk; ++t) lb.push_back(make_int2((int)i, t));
       for (int t = 0; t < mb->plan.nslice; ++t) sl.push_back(make_int2((int)i, t));
-      lds_fwd = std::max(lds_fwd, lds_forward_floats(mb->plan, kp));
-      lds_adj = std::max(lds_adj, lds_adjoint_floats(mb->plan, kp));
+      lds_fwd = std::max(lds_fwd, lds_forward_floats(mb->plan, kp, split));
+      lds_adj = std::max(lds_adj, lds_adjoint_floats(mb->plan, kp, split));
     }
     // ICNNM_GATHER=generic keeps the position-owning gather everywhere (compares the
     // two gathers; every plan's box fits both)
@@ -575,8 +607,9 @@ struct Group {
     a.k = k;
     a.kt = kt;
     a.u16 = prec != kFP32 ? 1 : 0;
-    a.nsg = nsg;
-    a.ncg = ncg;
+    a.split = split ? 1 : 0;
+    a.nsg = split ? kp / kColUnit : nsg;
+    a.ncg = split ? kp / kColUnit : ncg;
     a.ntiles = ntiles_total;
     a.tiles_per_slice = kTilesPerSlice;
     a.prec = prec;
@@ -1022,12 +1055,18 @@ static Plan choose_plan(icnnm_ctx* c, const int m[3], const int kd[3], int kp, i
                         bool may_measure = true) {
   int kdp[3];
   contraction_dims(kd, prec, kdp);
-  auto base_plan = [&] { return same_class ? make_plan_shared(m, kdp, kp) : make_plan(m, kdp, kp); };
+  // an instance solved alone may take the split contractions; members of joint
+  // launches never do
+  auto split_of = [&](Plan p) {
+    if (!same_class) decide_split(p, kp, prec);
+    return p;
+  };
+  auto base_plan = [&] { return split_of(same_class ? make_plan_shared(m, kdp, kp) : make_plan(m, kdp, kp)); };
   if (!autotune_on() || getenv("ICNNM_TILE")) return base_plan();
   load_tune_cache(c);
   const std::string key = tune_key(m, kd, prec, same_class ? 1 : 0);
   auto it = c->tuned.find(key);
-  if (it != c->tuned.end()) return plan_with_box(m, kdp, kp, it->second.data());
+  if (it != c->tuned.end()) return split_of(plan_with_box(m, kdp, kp, it->second.data()));
   if (!may_measure) return base_plan();
   auto all = plan_candidates(m, kdp, kp);
   if (all.empty()) throw Error(ICNNM_E_INVALID, "no tile shape fits this problem");
@@ -1044,6 +1083,7 @@ static Plan choose_plan(icnnm_ctx* c, const int m[3], const int kd[3], int kp, i
   for (int i = 0; i < (int)cands.size(); ++i) {
     Plan p = cands[i];
     finish_plan(p, kp);
+    p = split_of(p);
     double t = 1e300;
     try {
       t = time_plan(c, p, kd, prec, M, mask, V, st);
@@ -1061,6 +1101,7 @@ static Plan choose_plan(icnnm_ctx* c, const int m[3], const int kd[3], int kp, i
   if (best_t >= 1e300) return base_plan();  // nothing could be timed
   Plan p = cands[best];
   finish_plan(p, kp);
+  p = split_of(p);
   c->tuned[key] = {p.b[0], p.b[1], p.b[2]};
   save_tune_entry(key, p.b);
   return p;
@@ -1069,6 +1110,7 @@ static Plan choose_plan(icnnm_ctx* c, const int m[3], const int kd[3], int kp, i
 static void fill_tile(const Plan& p, icnnm_info* info) {
   if (!info) return;
   for (int d = 0; d < 3; ++d) info->tile[d] = p.b[d];
+  info->split = p.split ? 1 : 0;
 }
 
 static icnnm_status do_solve(icnnm_ctx* c, const icnnm_shape* shape, const float* M, const uint8_t* mask,
@@ -1274,10 +1316,10 @@ static std::mutex& scratch_lock(int device) {
 }
 
 // bytes of the scratch a solve of plan p takes (bump order of do_solve_noalloc)
-static size_t noalloc_bytes(const Plan& p, int kp, int nsg, int prec) {
+static size_t noalloc_bytes(const Plan& p, int kp, int prec) {
   size_t b = 256;                                                   // check_v result
   b += align256(sizeof(InstState));                                  // state slot
-  b += align256(member_bytes(p, kp, nsg, nsg, prec));                // instance state
+  b += align256(member_bytes(p, kp, prec));                          // instance state
   b += 3 * align256((size_t)kp * kp * 4);                            // V layouts (FP32)
   if (prec != kFP32) b += 3 * align256((size_t)kp * kp * 2);         // V layouts (16-bit)
   b += align256(2 * sizeof(InstDev)) + 3 * align256(2 * 8 * ((size_t)p.ntiles + p.nlblk + p.nslice));  // tables
@@ -1297,13 +1339,14 @@ static icnnm_status do_solve_noalloc(icnnm_ctx* c, const icnnm_shape* shape, con
   int kdp[3];
   contraction_dims(kd, params->precision, kdp);
   const int kc = kdp[0] * kdp[1] * kdp[2];
-  const int kp = padded_k(kc), nsg = (kp + kGroup - 1) / kGroup;
+  const int kp = padded_k(kc);
   Budget arena;  // outlives every buffer carved from it
   arena.arena = c->scratch;
   arena.limit = kNoAllocBytes;
   Member mb;
   mb.plan = make_plan(m, kdp, kp);  // the cost model's box (no measurement: it would allocate)
-  const size_t need = noalloc_bytes(mb.plan, kp, nsg, params->precision) + (kc != k ? (size_t)kc * kc * 4 + 256 : 0);
+  decide_split(mb.plan, kp, params->precision);
+  const size_t need = noalloc_bytes(mb.plan, kp, params->precision) + (kc != k ? (size_t)kc * kc * 4 + 256 : 0);
   if (need > kNoAllocBytes)
     throw Error(ICNNM_E_BUDGET, "instance needs " + std::to_string(need) + " bytes of solver state, above the " +
                                     std::to_string(kNoAllocBytes >> 20) + " MiB allocation-free scratch maximum");
@@ -1618,15 +1661,17 @@ icnnm_status icnnm_plan(const icnnm_shape* shape, const icnnm_params* params, in
     check_precision_shape(m, kd, params);
     int kdp[3];
     contraction_dims(kd, params->precision, kdp);
-    const int kp = padded_k(kdp[0] * kdp[1] * kdp[2]), nsg = (kp + kGroup - 1) / kGroup;
-    const Plan p = joint ? make_plan_shared(m, kdp, kp) : make_plan(m, kdp, kp);
+    const int kp = padded_k(kdp[0] * kdp[1] * kdp[2]);
+    Plan p = joint ? make_plan_shared(m, kdp, kp) : make_plan(m, kdp, kp);
+    if (!joint) decide_split(p, kp, params->precision);
     for (int d = 0; d < 3; ++d) {
       out->tile[d] = p.b[d];
       out->tiles_per_dim[d] = p.nt[d];
     }
     out->ntiles = p.ntiles;
     out->padded_k = kp;
-    out->state_bytes = (int64_t)member_bytes(p, kp, nsg, nsg, params->precision);
+    out->state_bytes = (int64_t)member_bytes(p, kp, params->precision);
+    out->split = p.split ? 1 : 0;
     return ICNNM_OK;
   } catch (const Error& e) {
     return e.code;
@@ -1899,11 +1944,10 @@ static icnnm_status do_submit(icnnm_ctx* c, const icnnm_shape* shape, const floa
   contraction_dims(r.kd, params->precision, kdp);
   const int kc = kdp[0] * kdp[1] * kdp[2];
   const int kp = padded_k(kc);
-  const int nsg = (kp + kGroup - 1) / kGroup;
   const Plan p = make_plan_shared(r.m, kdp, kp);  // as the server will plan it
   // the member's state, plus its entries in the group's descriptor and tile tables
   // (which grow by doubling)
-  r.bytes = member_bytes(p, kp, nsg, nsg, params->precision) +
+  r.bytes = member_bytes(p, kp, params->precision) +
             2 * align256(sizeof(InstDev) + 8 * ((size_t)p.ntiles + p.nlblk + p.nslice));
   // a new group: V operand copies (three FP32 layouts, three more in BF16/FP16 for the
   // reduced precisions) and the state array of its slots

@@ -43,7 +43,8 @@ class Params(C.Structure):
 class Info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("r_primal", C.c_double),
                 ("r_change", C.c_double), ("objective", C.c_double), ("theta_final", C.c_double),
-                ("t_queue_s", C.c_double), ("t_device_s", C.c_double), ("tile", C.c_int32 * 3)]
+                ("t_queue_s", C.c_double), ("t_device_s", C.c_double), ("tile", C.c_int32 * 3),
+                ("split", C.c_int32)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -53,7 +54,7 @@ class Info(C.Structure):
 
 class PlanInfo(C.Structure):
     _fields_ = [("tile", C.c_int32 * 3), ("tiles_per_dim", C.c_int32 * 3), ("ntiles", C.c_int32),
-                ("padded_k", C.c_int32), ("state_bytes", C.c_int64)]
+                ("padded_k", C.c_int32), ("state_bytes", C.c_int64), ("split", C.c_int32)]
 
 
 class IcnnmError(RuntimeError):
@@ -127,8 +128,8 @@ def make_params(lib, max_iter=100, lam=math.inf, theta0=0.0, rho=1.1, theta_max=
 
 def plan(dims, kdims, joint=False, lib=None, **kw):
     """Host-only tile plan of one instance (icnnm_plan; no GPU needed). Returns a dict
-    with the tile box, tiles per dimension, tile count, padded k and state bytes, or
-    raises IcnnmError."""
+    with the tile box, tiles per dimension, tile count, padded k, state bytes and
+    whether the contractions take their split form, or raises IcnnmError."""
     lib = lib or load_library()
     shape = make_shape(dims, kdims)
     p = make_params(lib, **kw)
@@ -137,7 +138,7 @@ def plan(dims, kdims, joint=False, lib=None, **kw):
     if rc != OK:
         raise IcnnmError(rc, "icnnm_plan failed")
     return {"tile": tuple(out.tile), "tiles_per_dim": tuple(out.tiles_per_dim), "ntiles": int(out.ntiles),
-            "padded_k": int(out.padded_k), "state_bytes": int(out.state_bytes)}
+            "padded_k": int(out.padded_k), "state_bytes": int(out.state_bytes), "split": bool(out.split)}
 
 
 def _ptr(t):

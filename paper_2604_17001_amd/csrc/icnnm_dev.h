@@ -88,6 +88,7 @@ struct StageArgs {
   int32_t kt;               // offsets of the kernel itself: the 1/k of the L-step
   int32_t u16;              // U stored in 16 bits (the instances' precision is BF16/FP16)
   int32_t ntiles;        // entries of `tiles`
+  int32_t nlblocks;      // entries of `lblocks`
   int32_t tiles_per_slice;
   int32_t prec;
   int32_t split;         // split contractions: 64-column (offset) groups, the kernel

@@ -1401,7 +1401,14 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
 // =====================================================================================
 template <int KG>
 __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
-  const int2 lb = a.lblocks[blockIdx.x];
+  // Workgroup w runs on XCD w % 8; the blocks are dealt so that each XCD takes one
+  // contiguous run of them, in order: neighbouring output blocks read adjacent rows of
+  // the same tiles' halo partials, so a cache line one block fetches is in that XCD's
+  // L2 for the next (results do not depend on the order).
+  const int nb8 = (a.nlblocks + 7) >> 3;
+  const int lbi = (int)(blockIdx.x & 7) * nb8 + (int)(blockIdx.x >> 3);
+  if (lbi >= a.nlblocks) return;
+  const int2 lb = a.lblocks[lbi];
   const InstDev& I = a.inst[lb.x];
   const int phase = I.st->phase;
   if (phase != kInit && phase != kRun) return;
@@ -1976,10 +1983,15 @@ void launch_adjoint(const StageArgs& a, int ntiles_total, int lds_floats, int mo
 }
 
 void launch_lstep(const StageArgs& a, int nlblocks_total, hipStream_t st) {
-  if (a.nsg == 1)
-    hipLaunchKernelGGL(k_lstep<1>, dim3(nlblocks_total), dim3(kThreads), 0, st, a);
+  // the four-group fast path (more registers) only where its shapes occur: the split
+  // form's small tiles
+  StageArgs b = a;
+  b.nlblocks = nlblocks_total;
+  const dim3 g(((nlblocks_total + 7) / 8) * 8);
+  if (a.split)
+    hipLaunchKernelGGL(k_lstep<4>, g, dim3(kThreads), 0, st, b);
   else
-    hipLaunchKernelGGL(k_lstep<4>, dim3(nlblocks_total), dim3(kThreads), 0, st, a);
+    hipLaunchKernelGGL(k_lstep<1>, g, dim3(kThreads), 0, st, b);
 }
 
 template <bool KS>

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <functional>
 #include <limits>
 #include <mutex>
@@ -28,7 +29,9 @@ namespace {
 // Fixed set of worker threads running parallel_for over [0, n) in contiguous blocks.
 class Pool {
  public:
-  explicit Pool(int nt) {
+  // split_all: split every range over the threads, however small (a forced thread
+  // count, to run the threaded path on small matrices)
+  explicit Pool(int nt, bool split_all = false) : split_all_(split_all) {
     for (int t = 1; t < nt; ++t) th_.emplace_back([this, t] { work(t); });
     nt_ = nt;
   }
@@ -44,7 +47,7 @@ class Pool {
   // fn(begin, end) on blocks of [0, n), each with at least ~256K operations of work
   // (item_cost operations per index) to amortise the hand-off; small ranges run inline
   void parallel_for(int n, const std::function<void(int, int)>& fn, int64_t item_cost) {
-    const int64_t per = std::max<int64_t>(1, (int64_t(1) << 18) / std::max<int64_t>(1, item_cost));
+    const int64_t per = split_all_ ? 1 : std::max<int64_t>(1, (int64_t(1) << 18) / std::max<int64_t>(1, item_cost));
     const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(nt_, n / per));
     if (nt == 1) {
       fn(0, n);
@@ -90,10 +93,13 @@ class Pool {
   int n_ = 0, active_ = 1, pending_ = 0, nt_ = 1;
   uint64_t gen_ = 0;
   bool stop_ = false;
+  bool split_all_ = false;
 };
 
-// threads for an n x n problem: below ~1500 the hand-off cost outweighs the gain
+// threads for an n x n problem: below ~1500 the hand-off cost outweighs the gain;
+// ICNNM_EIG_THREADS=t forces t threads (runs the threaded path on small matrices)
 int pool_threads(int n) {
+  if (const char* e = std::getenv("ICNNM_EIG_THREADS")) return std::max(1, std::min(std::atoi(e), 64));
   const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
   return n < 1500 ? 1 : std::min(hw, 16);
 }
@@ -110,7 +116,7 @@ void sym_eig(std::vector<double>& A, int n, std::vector<double>& w, std::vector<
   std::vector<std::vector<double>> hv;  // Householder vectors (length n-k-1)
   std::vector<double> hb;
   std::vector<double> p(n), wv(n);
-  Pool pool(pool_threads(n));
+  Pool pool(pool_threads(n), std::getenv("ICNNM_EIG_THREADS") != nullptr);
 
   // --- tridiagonalisation: A <- H_k A H_k, k = 0..n-3
   for (int k = 0; k + 2 < n; ++k) {

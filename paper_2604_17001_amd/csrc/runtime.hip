@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "../../include/icnnm.h"
+#include "admission.h"
 #include "icnnm_dev.h"
 
 namespace icnnm {
@@ -359,15 +360,6 @@ static size_t member_bytes(const Plan& p, int kp, int prec) {
   b += align256(p.gtab.size() * 4);                          // gather tables
   if (prec != kFP32) b += 2 * align256((size_t)p.mtot * 4);  // Lprev, T
   return b;
-}
-
-// Contraction precision of round r of a member that joined at its round 0 (initial
-// forward in FP32; round r >= 1 runs iteration r): FP32 at initialisation, on the
-// first iteration, every refresh_every-th and from the last one on (the refresh
-// schedule of the column-norm kernel), the member's reduced precision otherwise.
-static int round_kind(int r, int prec, int max_iter, int refresh_every) {
-  if (prec == kFP32 || r == 0 || refresh_every <= 1 || r >= max_iter) return kFP32;
-  return (r - 1) % refresh_every == 0 ? (int)kFP32 : prec;
 }
 
 // Kernel dimensions the contractions run with. The reduced-precision forward reads
@@ -1754,42 +1746,25 @@ static void serve_loop(icnnm_ctx* c) {
       for (auto& kv : groups) any_active = any_active || !kv.second.active.empty();
       if (!any_active) c->q_cv.wait(lk, [&] { return c->stop || !c->queue.empty(); });
       if (c->stop && c->queue.empty() && !any_active) break;
-      // Admission. Bytes are reserved cumulatively within the pass; a request that
-      // opens a new group also reserves the group's V operand copies and state array,
-      // and a group takes at most kServeSlots members. Requests are taken in arrival
-      // order; when the head does not fit, up to kBypassScan later requests that do
-      // fit may pass it, at most kMaxBypass times per head, after which the queue
-      // waits for the head (no starvation).
-      size_t reserved = c->budget.used.load();
-      std::map<std::string, int> slots_left;
-      std::set<std::string> opened;
-      Request* blocked = nullptr;
-      int scanned = 0;
-      for (auto it = c->queue.begin(); it != c->queue.end();) {
-        if (blocked && (blocked->bypassed >= kMaxBypass || scanned >= kBypassScan)) break;
-        Request& r = *it;
-        const std::string key = group_key(r.V, r.kd, r.params.precision);
-        auto g = groups.find(key);
-        const bool exists = (g != groups.end() && g->second.g) || opened.count(key);
-        auto sl = slots_left.find(key);
-        if (sl == slots_left.end())
-          sl = slots_left.emplace(key, (g != groups.end() && g->second.g) ? (int)g->second.g->free_slots.size()
-                                                                           : kServeSlots).first;
-        const size_t need = r.bytes + (exists ? 0 : r.group_bytes);
-        if (blocked) ++scanned;
-        if (sl->second > 0 && reserved + need <= c->budget.limit) {
-          reserved += need;
-          sl->second -= 1;
-          opened.insert(key);
-          if (blocked) blocked->bypassed += 1;
-          admit.push_back(r);
-          it = c->queue.erase(it);
-          continue;
-        }
-        if (!blocked) blocked = &r;
-        ++it;
+      // Admission (admission_pass): cumulative reservation within the pass, a new
+      // group's bytes with its first request, at most kServeSlots members per group,
+      // bounded bypass of a blocked head.
+      std::vector<AdmitView> views;
+      std::vector<std::list<Request>::iterator> where;
+      for (auto it = c->queue.begin(); it != c->queue.end(); ++it) {
+        views.push_back(AdmitView{group_key(it->V, it->kd, it->params.precision), it->bytes, it->group_bytes, &it->bypassed});
+        where.push_back(it);
       }
-      head_blocked = blocked != nullptr && blocked == &c->queue.front();
+      std::map<std::string, int> free_slots;
+      for (auto& kv : groups)
+        if (kv.second.g) free_slots[kv.first] = (int)kv.second.g->free_slots.size();
+      const AdmitResult ar = admission_pass(
+          views, free_slots, AdmitLimits{c->budget.used.load(), c->budget.limit, kServeSlots, kMaxBypass, kBypassScan});
+      for (size_t i : ar.admitted) {
+        admit.push_back(*where[i]);
+        c->queue.erase(where[i]);
+      }
+      head_blocked = ar.head_blocked;
     }
     if (admit.empty() && head_blocked && !any_active) {
       // Nothing runs and the head does not fit: budget is held outside the server.

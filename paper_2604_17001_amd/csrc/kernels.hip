@@ -65,8 +65,8 @@ struct LowP<kFP16> {
 
 // Which contraction a stage kernel of mode MODE runs for an iterating instance:
 // FP32 on FP32 solves and on refresh iterations, the reduced precision otherwise.
-template <int MODE>
-__device__ __forceinline__ bool runs_iteration(const InstDev& I, const InstState* st) {
+template <int MODE, class Desc>
+__device__ __forceinline__ bool runs_iteration(const Desc& I, const InstState* st) {
   const bool full = (I.prec == kFP32) || st->refresh;
   return MODE == kFP32 ? full : (!full && I.prec == MODE);
 }
@@ -150,7 +150,8 @@ __device__ __forceinline__ float wave_sum(float x) {
 }
 
 // Offset of kernel offset s inside a box with strides (E1*E2, E2, 1); 0 for padding.
-__device__ __forceinline__ int kernel_off(int s, const InstDev& I, int k) {
+template <class Desc>
+__device__ __forceinline__ int kernel_off(int s, const Desc& I, int k) {
   if (s >= k) return 0;
   int s2 = s % I.k[2];
   int t = s / I.k[2];
@@ -161,7 +162,8 @@ __device__ __forceinline__ int kernel_off(int s, const InstDev& I, int k) {
 
 // Box position of tile row r (C order inside the tile box), shifted by (k - 1) so
 // that base - off(s) addresses row r's source (forward) or target (adjoint) t = r - s.
-__device__ __forceinline__ int row_base(int r, const InstDev& I, const int* o, bool& valid) {
+template <class Desc>
+__device__ __forceinline__ int row_base(int r, const Desc& I, const int* o, bool& valid) {
   int a2 = r % I.b[2];
   int t = r / I.b[2];
   int a1 = t % I.b[1];
@@ -170,7 +172,8 @@ __device__ __forceinline__ int row_base(int r, const InstDev& I, const int* o, b
   return ((a0 + I.k[0] - 1) * I.E[1] + (a1 + I.k[1] - 1)) * I.E[2] + (a2 + I.k[2] - 1);
 }
 
-__device__ __forceinline__ void tile_origin(int lt, const InstDev& I, int* o) {
+template <class Desc>
+__device__ __forceinline__ void tile_origin(int lt, const Desc& I, int* o) {
   int n2 = lt % I.nt[2];
   int t = lt / I.nt[2];
   int n1 = t % I.nt[1];
@@ -199,7 +202,8 @@ __device__ __forceinline__ int wrap3(int v, int m) {
 struct HaloMap {
   int E12, E2, s0, s1, s2, m0, m1, m2;  // s_d = tile origin - (k_d - 1)
   float r12, r2;
-  __device__ __forceinline__ HaloMap(const InstDev& I, const int* o) {
+  template <class Desc>
+  __device__ __forceinline__ HaloMap(const Desc& I, const int* o) {
     E2 = I.E[2];
     E12 = I.E[1] * E2;
     r12 = 1.f / (float)E12;
@@ -311,12 +315,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   static_assert(!KS || RB == 2, "the split form has 64-row units");
   extern __shared__ float smem[];
   const int2 tt = a.tiles[blockIdx.x];
-  const InstDev& I = a.inst[tt.x];
-  // The descriptor as constant memory, for the fields read between the epilogue's
-  // global stores: read through I after a store (which might alias it), each would be
-  // loaded again with a vector load and a wait for all outstanding loads, draining the
-  // prefetched state loads at every piece; constant loads go through the scalar cache.
-  const CInstDev* const Ic = (const CInstDev*)(a.inst + tt.x);
+  // The descriptor is read as constant memory: through a generic reference, a field
+  // read after a global store (which might alias it) is loaded again with a vector
+  // load and a wait for all outstanding loads, which drains the epilogue's prefetched
+  // state loads at every piece; constant loads go through the scalar cache.
+  const CInstDev& I = *(const CInstDev*)(a.inst + tt.x);
   const int phase = I.st->phase;
   if (MODE == kFP32) {
     if (phase != kInit && !(phase == kRun && runs_iteration<MODE>(I, I.st))) return;
@@ -355,20 +358,23 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   const HaloMap hm(I, o);
   if constexpr (MODE == kFP32) {
     // halo of L over the tile box extended backwards by k - 1, with circular wrap;
-    // eight positions per thread are loaded before any is stored
+    // eight positions per thread are loaded before any is stored. The loads are
+    // unconditional (positions past the box read box position 0, then discarded) and
+    // their values pass through an empty asm before the selection: otherwise the
+    // compiler turns the selection into a branch around each load, with the load's
+    // wait inside it, one load at a time.
     gcfloat* L = gc1(I.L);
     for (int xb = tid; xb < E123; xb += 8 * kThreads) {
       float v[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int x = xb + j * kThreads;
-        v[j] = 0.f;
-        if (x < E123) {
-          int c2;
-          const int64_t r = hm.row(x, c2);
-          v[j] = L[r + wrap3(c2, hm.m2)];
-        }
+        int c2;
+        const int64_t r = hm.row(x < E123 ? x : 0, c2);
+        v[j] = L[r + wrap3(c2, hm.m2)];
       }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) asm("" : "+v"(v[j]));
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int x = xb + j * kThreads;
@@ -383,23 +389,28 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
     typedef typename LowP<MODE>::h H;
     H* e4 = reinterpret_cast<H*>(halo);
     gcfloat* D = gc1(I.D);
-    // four positions per thread (16 values) are loaded before any is stored
+    // four positions per thread (16 values) are loaded before any is stored, all
+    // unconditionally (see the FP32 halo above): excluded entries read a valid
+    // address and are set to zero
     for (int xb = tid; xb < E123; xb += 4 * kThreads) {
       float v[4][4];
+      int x2v[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int x = xb + j * kThreads;
+        int c2;
+        const int64_t r = hm.row(x < E123 ? x : 0, c2);
+        x2v[j] = c2 - hm.s2;
 #pragma unroll
-        for (int d = 0; d < 4; ++d) v[j][d] = 0.f;
-        if (x < E123) {
-          int c2;
-          const int64_t r = hm.row(x, c2);
-          const int x2 = c2 - hm.s2;
-#pragma unroll
-          for (int d = 0; d < 4; ++d)
-            if (x2 >= d) v[j][d] = D[r + wrap3(c2 - d, hm.m2)];
-        }
+        for (int d = 0; d < 4; ++d) v[j][d] = D[r + wrap3(x2v[j] >= d ? c2 - d : c2, hm.m2)];
       }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          asm("" : "+v"(v[j][d]));
+          v[j][d] = x2v[j] >= d ? v[j][d] : 0.f;
+        }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int x = xb + j * kThreads;
@@ -453,16 +464,16 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
     UPiece bu[kAhead];
     auto load_piece = [&](int pc, int slot) {
       const int cb = pc / RB, ib = pc % RB;
-      const size_t pidx = ((size_t)lt * (Ic->bm / 32) + ru * RB + ib) * nkb + c0 / 32 + cb;
-      gcfloat4* Wp = gc4(Ic->W) + pidx * 256 + lane;
+      const size_t pidx = ((size_t)lt * (I.bm / 32) + ru * RB + ib) * nkb + c0 / 32 + cb;
+      gcfloat4* Wp = gc4(I.W) + pidx * 256 + lane;
 #pragma unroll
       for (int g = 0; g < 4; ++g) bw[slot][g] = Wp[g * 64];
       if constexpr (UB == 4) {
-        gcfloat4* Up = gc4(Ic->U) + pidx * 256 + lane;
+        gcfloat4* Up = gc4(I.U) + pidx * 256 + lane;
 #pragma unroll
         for (int g = 0; g < 4; ++g) bu[slot][g] = Up[g * 64];
       } else {
-        gcuint4* Up = gcu4(Ic->U) + pidx * 128 + lane;
+        gcuint4* Up = gcu4(I.U) + pidx * 128 + lane;
         bu[slot][0] = Up[0];
         bu[slot][1] = Up[64];
       }
@@ -657,7 +668,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
           s4[g] = make_float4(0.f, 0.f, 0.f, 0.f);
-          if constexpr (!kFirst) s4[g] = *gc4(Ic->s + cblk * 32 + g * 8 + half * 4);
+          if constexpr (!kFirst) s4[g] = *gc4(I.s + cblk * 32 + g * 8 + half * 4);
         }
         float qs[16], ws[16];
 #pragma unroll
@@ -685,9 +696,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
             }
             if (!KS && pc + kAhead < kPieces) load_piece(pc + kAhead, slot);
           }
-          const size_t pidx = ((size_t)lt * (Ic->bm / 32) + ru * RB + ib) * nkb + cblk;
-          gfloat4* Wp = g4(Ic->W) + pidx * 256 + lane;
-          gfloat4* Up4 = g4(Ic->U) + pidx * 256 + lane;
+          const size_t pidx = ((size_t)lt * (I.bm / 32) + ru * RB + ib) * nkb + cblk;
+          gfloat4* Wp = g4(I.W) + pidx * 256 + lane;
+          gfloat4* Up4 = g4(I.U) + pidx * 256 + lane;
           float unv[UB == 2 ? 16 : 1];
 #pragma unroll
           for (int g = 0; g < 4; ++g) {
@@ -739,7 +750,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
             if constexpr (UB == 4) Up4[g * 64] = make_float4(un[0], un[1], un[2], un[3]);
           }
           if constexpr (UB == 2) {
-            uint4* Up = reinterpret_cast<uint4*>(Ic->U) + pidx * 128 + lane;
+            uint4* Up = reinterpret_cast<uint4*>(I.U) + pidx * 128 + lane;
             Up[0] = u16_pack(unv, uscale);
             Up[64] = u16_pack(unv + 8, uscale);
           }

@@ -817,8 +817,8 @@ constexpr int kMaxOwnedBig = 24;  // ... of the large-kernel adjoints (E123 <= 6
 // col2im gather: thread-owned box position x (box coordinates) receives
 // H[j = x - (k - 1) + s][s] for the staged kernel offsets s in [S0, S1) whose row j
 // lies inside the tile; Hs[s - S0][row] holds the staged H^T. Fixed order.
-template <int CAP>
-__device__ __forceinline__ void gather_round(const InstDev& I, const float* Hs, int hstride, int S0, int S1,
+template <int CAP, class Desc>
+__device__ __forceinline__ void gather_round(const Desc& I, const float* Hs, int hstride, int S0, int S1,
                                              float* tacc) {
   const int k0 = I.k[0], k1 = I.k[1], k2 = I.k[2], k12 = k1 * k2;
   const int E123 = I.E123, E12 = I.E[1] * I.E[2];
@@ -866,8 +866,8 @@ __device__ __forceinline__ bool adjoint_item(const StageArgs& a, int2& tt, int& 
 // H[(j0, j1, j2)][(p, q, r)] (contiguous in j2, read as float4) is added along its
 // anti-diagonals x2 = j2 + 3 - r. Every position receives its terms in the same
 // (p, q, r) order as gather_round, so both give identical sums.
-template <int B2, int LMAX>
-__device__ __forceinline__ void gather_lines(const InstDev& I, const float* Hs, int hstride, int S0, int S1,
+template <int B2, int LMAX, class Desc>
+__device__ __forceinline__ void gather_lines(const Desc& I, const float* Hs, int hstride, int S0, int S1,
                                              float (&lacc)[LMAX][B2 + 3]) {
   const int k0 = I.k[0], k1 = I.k[1];
   const int E1 = I.E[1], nl = I.E[0] * E1;
@@ -917,10 +917,12 @@ struct GatherAcc<0, CAP> {
 #pragma unroll
     for (int i = 0; i < CAP; ++i) t[i] = 0.f;
   }
-  __device__ __forceinline__ void round(const InstDev& I, const float* Hs, int hstride, int S0, int S1) {
+  template <class Desc>
+  __device__ __forceinline__ void round(const Desc& I, const float* Hs, int hstride, int S0, int S1) {
     gather_round<CAP>(I, Hs, hstride, S0, S1, t);
   }
-  __device__ __forceinline__ void store(const InstDev& I, float* dst) const {
+  template <class Desc>
+  __device__ __forceinline__ void store(const Desc& I, float* dst) const {
 #pragma unroll
     for (int i = 0; i < CAP; ++i) {
       const int x = threadIdx.x + i * kThreads;
@@ -940,10 +942,12 @@ struct GatherAcc<8, CAP> {
 #pragma unroll
       for (int j = 0; j < kE2; ++j) t[i][j] = 0.f;
   }
-  __device__ __forceinline__ void round(const InstDev& I, const float* Hs, int hstride, int S0, int S1) {
+  template <class Desc>
+  __device__ __forceinline__ void round(const Desc& I, const float* Hs, int hstride, int S0, int S1) {
     gather_lines<8, kLines>(I, Hs, hstride, S0, S1, t);
   }
-  __device__ __forceinline__ void store(const InstDev& I, float* dst) const {
+  template <class Desc>
+  __device__ __forceinline__ void store(const Desc& I, float* dst) const {
     const int nl = I.E[0] * I.E[1];
 #pragma unroll
     for (int i = 0; i < kLines; ++i) {
@@ -958,8 +962,8 @@ struct GatherAcc<8, CAP> {
 // Loads of the state for the adjoint's G: the eight values 8p..8p+7 of one lane (the
 // float4 groups 2p and 2p + 1 of the tile layout) of W and of U for the piece at
 // piece index pidx, with Q = W - U returned in place of W.
-template <int UB>
-__device__ __forceinline__ void load_uq8(const InstDev& I, size_t pidx, int p, int lane, float uinv, float4 (&u)[2],
+template <int UB, class Desc>
+__device__ __forceinline__ void load_uq8(const Desc& I, size_t pidx, int p, int lane, float uinv, float4 (&u)[2],
                                          float4 (&q)[2]) {
   gcfloat4* W4 = gc4(I.W) + pidx * 256 + 2 * p * 64 + lane;
   const float4 w0 = W4[0], w1 = W4[64];
@@ -987,7 +991,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
   int2 tt;
   int sg;
   if (!adjoint_item(a, tt, sg)) return;
-  const InstDev& I = a.inst[tt.x];
+  // constant descriptor (see k_forward) with the line gather; the position gather keeps
+  // the generic one (with constant fields its per-thread accumulators spill)
+  typedef typename std::conditional<GV == 8, const CInstDev, const InstDev>::type Desc;
+  Desc& I = *(Desc*)(a.inst + tt.x);
   if (I.st->phase != kRun || !runs_iteration<MODE>(I, I.st)) return;
   const int kp = a.kp, k = a.k;
   const int SGW = KS ? kColUnit : (kp < kGroup ? kp : kGroup);
@@ -1184,7 +1191,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big(StageArgs a) {
   int2 tt;
   int sg;
   if (!adjoint_item(a, tt, sg)) return;
-  const InstDev& I = a.inst[tt.x];
+  // constant descriptor (see k_forward) with the line gather; the position gather keeps
+  // the generic one (with constant fields its per-thread accumulators spill)
+  typedef typename std::conditional<GV == 8, const CInstDev, const InstDev>::type Desc;
+  Desc& I = *(Desc*)(a.inst + tt.x);
   if (I.st->phase != kRun || !runs_iteration<kFP32>(I, I.st)) return;
   const int kp = a.kp, k = a.k;
   const int lt = tt.y;
@@ -1308,7 +1318,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
   int2 tt;
   int sg;
   if (!adjoint_item(a, tt, sg)) return;
-  const InstDev& I = a.inst[tt.x];
+  // constant descriptor (see k_forward) with the line gather; the position gather keeps
+  // the generic one (with constant fields its per-thread accumulators spill)
+  typedef typename std::conditional<GV == 8, const CInstDev, const InstDev>::type Desc;
+  Desc& I = *(Desc*)(a.inst + tt.x);
   if (I.st->phase != kRun || !runs_iteration<MODE>(I, I.st)) return;
   const int kp = a.kp, k = a.k;
   const int lt = tt.y;
@@ -1428,7 +1441,7 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
   const int lbi = (int)(blockIdx.x & 7) * nb8 + (int)(blockIdx.x >> 3);
   if (lbi >= a.nlblocks) return;
   const int2 lb = a.lblocks[lbi];
-  const InstDev& I = a.inst[lb.x];
+  const CInstDev& I = *(const CInstDev*)(a.inst + lb.x);  // constant: see k_forward
   const int phase = I.st->phase;
   if (phase != kInit && phase != kRun) return;
   // kLanesPerElem lanes share one output element; each sums every kLanesPerElem-th
@@ -1588,7 +1601,7 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
 // =====================================================================================
 __global__ __launch_bounds__(kThreads) void k_colnorm_reduce(StageArgs a) {
   const int2 sl = a.slices[blockIdx.x];
-  const InstDev& I = a.inst[sl.x];
+  const CInstDev& I = *(const CInstDev*)(a.inst + sl.x);  // constant: see k_forward
   const int phase = I.st->phase;
   if (phase != kInit && phase != kRun) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1645,7 +1658,7 @@ __global__ __launch_bounds__(kThreads) void k_colnorm_reduce(StageArgs a) {
 }
 
 __global__ __launch_bounds__(kThreads) void k_colnorm_finish(StageArgs a) {
-  const InstDev& I = a.inst[blockIdx.x];
+  const CInstDev& I = *(const CInstDev*)(a.inst + blockIdx.x);  // constant: see k_forward
   InstState* st = I.st;
   const int phase = st->phase;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;

@@ -960,31 +960,46 @@ struct GatherAcc<8, CAP> {
 };
 
 // Loads of the state for the adjoint's G: the eight values 8p..8p+7 of one lane (the
-// float4 groups 2p and 2p + 1 of the tile layout) of W and of U for the piece at
-// piece index pidx, with Q = W - U returned in place of W.
+// float4 groups 2p and 2p + 1 of the tile layout) of W and of U for the piece at piece
+// index pidx, kept as loaded (U in its stored width); split_uq8 then returns U and
+// Q = W - U. The two steps are apart so that a prefetch's values are first used, and
+// waited for, only where they are consumed, not right after the loads are issued.
+template <int UB>
+struct UQ8 {
+  float4 w[2];
+  typename std::conditional<UB == 4, float4[2], uint4>::type u;
+};
+
 template <int UB, class Desc>
-__device__ __forceinline__ void load_uq8(const Desc& I, size_t pidx, int p, int lane, float uinv, float4 (&u)[2],
-                                         float4 (&q)[2]) {
+__device__ __forceinline__ void load_uq8(const Desc& I, size_t pidx, int p, int lane, UQ8<UB>& r) {
   gcfloat4* W4 = gc4(I.W) + pidx * 256 + 2 * p * 64 + lane;
-  const float4 w0 = W4[0], w1 = W4[64];
+  r.w[0] = W4[0];
+  r.w[1] = W4[64];
   if constexpr (UB == 4) {
     gcfloat4* U4 = gc4(I.U) + pidx * 256 + 2 * p * 64 + lane;
-    u[0] = U4[0];
-    u[1] = U4[64];
+    r.u[0] = U4[0];
+    r.u[1] = U4[64];
+  } else {
+    r.u = gcu4(I.U)[pidx * 128 + p * 64 + lane];
+  }
+}
+
+template <int UB>
+__device__ __forceinline__ void split_uq8(const UQ8<UB>& r, float uinv, float4 (&u)[2], float4 (&q)[2]) {
+  if constexpr (UB == 4) {
+    u[0] = r.u[0];
+    u[1] = r.u[1];
   } else {
     float v[8];
-    u16_unpack(gcu4(I.U)[pidx * 128 + p * 64 + lane], uinv, v);
+    u16_unpack(r.u, uinv, v);
     u[0] = make_float4(v[0], v[1], v[2], v[3]);
     u[1] = make_float4(v[4], v[5], v[6], v[7]);
   }
+  const float4 w0 = r.w[0], w1 = r.w[1];
   q[0] = make_float4(w0.x - u[0].x, w0.y - u[0].y, w0.z - u[0].z, w0.w - u[0].w);
   q[1] = make_float4(w1.x - u[1].x, w1.y - u[1].y, w1.z - u[1].z, w1.w - u[1].w);
 }
 
-// Split form (KS, for launches with few tiles): offset groups of 64, one round, and
-// the four wavefronts share each unit (64 rows x 64 offsets), every one contracting a
-// quarter of the eigendirections; the partial sums meet in LDS in a fixed order and
-// each wavefront stages one 32 x 32 piece of H^T.
 template <int MODE, int GV, int UB, bool KS>
 __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
   extern __shared__ float smem[];
@@ -1038,11 +1053,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
     const size_t row0 = ((size_t)lt * (bm / 32) + rc * 2) * nkb;  // row group jb: (row0 + jb * nkb + cb)
     // operands of half block h (column block cb = h/2, part p = h%2); each iteration
     // consumes the loads of the previous one before issuing its own
-    float4 fu[2][2], fq[2][2], fs[2], fv[2][2];
+    UQ8<UB> fr[2];
+    float4 fs[2], fv[2][2];
     auto load = [&](int h) {
       const int cb = h >> 1, p = h & 1;
 #pragma unroll
-      for (int jb = 0; jb < 2; ++jb) load_uq8<UB>(I, row0 + (size_t)jb * nkb + cb, p, lane, uinv, fu[jb], fq[jb]);
+      for (int jb = 0; jb < 2; ++jb) load_uq8<UB>(I, row0 + (size_t)jb * nkb + cb, p, lane, fr[jb]);
       fs[0] = *gc4(S + cb * 32 + (2 * p) * 8 + half * 4);
       fs[1] = *gc4(S + cb * 32 + (2 * p + 1) * 8 + half * 4);
       const size_t ov = (size_t)cb * 256 + 2 * p;
@@ -1054,6 +1070,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
     load(hb0);
     for (int h = hb0; h < hb1; ++h) {
       float g[2][8];
+      float4 fu[2][2], fq[2][2];
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb) split_uq8<UB>(fr[jb], uinv, fu[jb], fq[jb]);
 #pragma unroll
       for (int jb = 0; jb < 2; ++jb) {
 #pragma unroll
@@ -1086,12 +1105,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
     gcuint4* va0 = gcu4(a.Va_lo) + (size_t)(s0 / 32) * nkb * 128 + lane;
     gcuint4* va1 = va0 + (size_t)nkb * 128;
     const size_t row0 = ((size_t)lt * (bm / 32) + rc * 2) * nkb;
-    float4 fu[2][2], fq[2][2], fs[2];
+    UQ8<UB> fr[2];
+    float4 fs[2];
     uint4 fv0, fv1;
     auto load = [&](int h) {
       const int cb = h >> 1, p = h & 1;
 #pragma unroll
-      for (int jb = 0; jb < 2; ++jb) load_uq8<UB>(I, row0 + (size_t)jb * nkb + cb, p, lane, uinv, fu[jb], fq[jb]);
+      for (int jb = 0; jb < 2; ++jb) load_uq8<UB>(I, row0 + (size_t)jb * nkb + cb, p, lane, fr[jb]);
       fs[0] = *gc4(S + cb * 32 + (2 * p) * 8 + half * 4);
       fs[1] = *gc4(S + cb * 32 + (2 * p + 1) * 8 + half * 4);
       fv0 = va0[(size_t)h * 64];
@@ -1100,6 +1120,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
     load(hb0);
     for (int h = hb0; h < hb1; ++h) {
       V8 g[2];
+      float4 fu[2][2], fq[2][2];
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb) split_uq8<UB>(fr[jb], uinv, fu[jb], fq[jb]);
 #pragma unroll
       for (int jb = 0; jb < 2; ++jb) {
 #pragma unroll
@@ -1219,10 +1242,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big(StageArgs a) {
   const float* vrow = a.Vp + (size_t)(sg * kGroup + tid) * kp;
   // two register slots: the loads of chunk q + 2 are issued while chunk q is
   // contracted, so each chunk's global loads have two contraction phases to land
-  float4 cu[2][2], cq[2][2], cs[2][2], cv[2][4];  // [slot][...]
+  UQ8<UB> cr[2];
+  float4 cs[2][2], cv[2][4];  // [slot][...]
   auto coop_load = [&](int q, int sl) {
     const int cb = q >> 1, p = q & 1;
-    load_uq8<UB>(I, ((size_t)lt * 4 + rg) * nkb + cb, p, lane, uinv, cu[sl], cq[sl]);
+    load_uq8<UB>(I, ((size_t)lt * 4 + rg) * nkb + cb, p, lane, cr[sl]);
     cs[sl][0] = *gc4(I.s + cb * 32 + (2 * p) * 8 + hf * 4);
     cs[sl][1] = *gc4(I.s + cb * 32 + (2 * p + 1) * 8 + hf * 4);
     gcfloat4* vp = gc4(vrow + q * kBigChunk);
@@ -1232,12 +1256,14 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big(StageArgs a) {
   auto coop_store = [&](int buf, int sl) {
     // G values of v = 8p..8p+7 sit at chunk columns (v%8/4)*8 + hf*4 + v%4
     float* gd = Gs + ((size_t)buf * 128 + rg * 32 + (lane & 31)) * kBigPad + hf * 4;
+    float4 cu[2], cq[2];
+    split_uq8<UB>(cr[sl], uinv, cu, cq);
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      gd[8 * t + 0] = cu[sl][t].x + cs[sl][t].x * cq[sl][t].x;
-      gd[8 * t + 1] = cu[sl][t].y + cs[sl][t].y * cq[sl][t].y;
-      gd[8 * t + 2] = cu[sl][t].z + cs[sl][t].z * cq[sl][t].z;
-      gd[8 * t + 3] = cu[sl][t].w + cs[sl][t].w * cq[sl][t].w;
+      gd[8 * t + 0] = cu[t].x + cs[sl][t].x * cq[t].x;
+      gd[8 * t + 1] = cu[t].y + cs[sl][t].y * cq[t].y;
+      gd[8 * t + 2] = cu[t].z + cs[sl][t].z * cq[t].z;
+      gd[8 * t + 3] = cu[t].w + cs[sl][t].w * cq[t].w;
     }
     float* vd = Vs + ((size_t)buf * 256 + tid) * kBigPad;
 #pragma unroll
@@ -1349,11 +1375,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
   const int vr = wave * 64 + (lane >> 2), vf = lane & 3;
   gcfloat4* vrow = gc4(a.Vp_lo) + (size_t)(sg * kGroup + vr) * (kp / 8) + vf;
   const size_t vstep = (size_t)16 * (kp / 8);
-  float4 cu[4], cq[4], cv0, cv1, cv2, cv3;
+  UQ8<2> cr[2];
+  float4 cv0, cv1, cv2, cv3;
   auto coop_load = [&](int cb) {
     const size_t pidx = ((size_t)lt * 4 + rg) * nkb + cb;
-    load_uq8<2>(I, pidx, 0, lane, uinv, reinterpret_cast<float4(&)[2]>(cu[0]), reinterpret_cast<float4(&)[2]>(cq[0]));
-    load_uq8<2>(I, pidx, 1, lane, uinv, reinterpret_cast<float4(&)[2]>(cu[2]), reinterpret_cast<float4(&)[2]>(cq[2]));
+    load_uq8<2>(I, pidx, 0, lane, cr[0]);
+    load_uq8<2>(I, pidx, 1, lane, cr[1]);
     cv0 = vrow[cb * 4];
     cv1 = vrow[vstep + cb * 4];
     cv2 = vrow[2 * vstep + cb * 4];
@@ -1362,6 +1389,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
   auto coop_store = [&](int buf, int cb) {
     // value v = 4g + e of the tile layout sits at column acc_col(v, hf) = 8g + 4hf + e
     H* gd = Gs + ((size_t)buf * 128 + rg * 32 + (lane & 31)) * kBigLpPad + hf * 4;
+    float4 cu[4], cq[4];
+    split_uq8<2>(cr[0], uinv, reinterpret_cast<float4(&)[2]>(cu[0]), reinterpret_cast<float4(&)[2]>(cq[0]));
+    split_uq8<2>(cr[1], uinv, reinterpret_cast<float4(&)[2]>(cu[2]), reinterpret_cast<float4(&)[2]>(cq[2]));
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const float4 sv = *reinterpret_cast<const float4*>(Ss + cb * 32 + g * 8 + hf * 4);

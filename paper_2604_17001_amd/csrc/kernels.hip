@@ -1509,8 +1509,8 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
     const int C1 = I.C[1], C2 = I.C[2];
     const int npair = I.C[0] * C1;
     const int gsh = I.gshift, gmask = (1 << gsh) - 1;  // entry = (tile << gsh) | position
-    // fast path: C2 <= 4, <= 4 pairs per lane, <= KG offset groups (1, or 4 for the
-    // split form's four per 256 offsets); same summation order as the general loop below
+    // fast path: C2 <= 4, <= 4 pairs per lane, <= KG offset groups (1, or 4 for
+    // launches with several); same summation order as the general loop below
     constexpr int kC2 = 4, kPr = 4, kG = KG;
     if (C2 <= kC2 && nsg <= kG && npair <= kPr * kLanesPerElem) {
       int e2v[kC2];
@@ -1551,6 +1551,35 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
         for (int c2 = 0; c2 < kC2; ++c2)
 #pragma unroll
           for (int g = 0; g < kG; ++g) T += v[j][c2][g];
+    } else if (C2 <= kC2 && nsg <= kG) {
+      // any number of pairs, one at a time: the pair's table entries, then all of its
+      // (c2, offset group) partials at once (two memory latencies per pair instead of
+      // one per partial); same summation order
+      int e2v[kC2];
+#pragma unroll
+      for (int c2 = 0; c2 < kC2; ++c2) e2v[c2] = c2 < C2 ? g2[c2] : -1;
+      for (int pr = sub; pr < npair; pr += kLanesPerElem) {
+        const int c0 = pr / C1, c1 = pr - c0 * C1;
+        const int e0 = g0[c0], e1 = g1[c1];
+        const bool okp = (e0 | e1) >= 0;
+        const int tb = ((e0 >> gsh) * I.nt[1] + (e1 >> gsh)) * I.nt[2];
+        const int pb = ((e0 & gmask) * I.E[1] + (e1 & gmask)) * I.E[2];
+        float v[kC2][kG];
+#pragma unroll
+        for (int c2 = 0; c2 < kC2; ++c2) {
+          const int e2 = e2v[c2];
+          const float* pp = I.part + ((size_t)(tb + (e2 >> gsh)) * nsg) * I.E123 + pb + (e2 & gmask);
+#pragma unroll
+          for (int g = 0; g < kG; ++g) {
+            v[c2][g] = 0.f;
+            if (okp && e2 >= 0 && g < nsg) v[c2][g] = pp[(size_t)g * I.E123];
+          }
+        }
+#pragma unroll
+        for (int c2 = 0; c2 < kC2; ++c2)
+#pragma unroll
+          for (int g = 0; g < kG; ++g) T += v[c2][g];
+      }
     } else {
       for (int pr = sub; pr < npair; pr += kLanesPerElem) {
         const int c0 = pr / C1, c1 = pr - c0 * C1;
@@ -2045,12 +2074,12 @@ void launch_adjoint(const StageArgs& a, int ntiles_total, int lds_floats, int mo
 }
 
 void launch_lstep(const StageArgs& a, int nlblocks_total, hipStream_t st) {
-  // the four-group fast path (more registers) only where its shapes occur: the split
-  // form's small tiles
+  // the four-group paths (more registers) only for launches with several offset
+  // groups (the split form; kp of 512 and more)
   StageArgs b = a;
   b.nlblocks = nlblocks_total;
   const dim3 g(((nlblocks_total + 7) / 8) * 8);
-  if (a.split)
+  if (a.nsg > 1)
     hipLaunchKernelGGL(k_lstep<4>, g, dim3(kThreads), 0, st, b);
   else
     hipLaunchKernelGGL(k_lstep<1>, g, dim3(kThreads), 0, st, b);

@@ -1495,6 +1495,14 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
       t0 = (int)(r / I.m[1]);
     }
   }
+  // the element's own inputs are loaded first, so that their latency overlaps the
+  // gather (lanes past the tensor read element 0 and discard it)
+  const int64_t tc = in ? t : 0;
+  const bool obs = I.mask[tc] != 0;
+  const float mv = I.M[tc];
+  const float lold = I.L[tc];
+  float tprev = 0.f;
+  if (I.prec != kFP32) tprev = I.T[tc];
   if (in && phase == kRun) {
     // partials of this iteration's adjoint: the full A_k^*(G V^T), or on a reduced
     // precision iteration its change since the previous one
@@ -1599,8 +1607,6 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
 #pragma unroll
   for (int o = 1; o < kLanesPerElem; o <<= 1) T += __shfl_xor(T, o, 64);
   if (in && sub == 0) {
-    const bool obs = I.mask[t] != 0;
-    const float mv = I.M[t];
     if (phase == kInit) {
       const float lv = obs ? mv : 0.f;
       I.L[t] = lv;
@@ -1608,7 +1614,7 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
     } else {
       float tk = T / (float)a.kt;
       if (I.prec != kFP32) {
-        if (!I.st->refresh) tk += I.T[t];
+        if (!I.st->refresh) tk += tprev;
         I.T[t] = tk;
       }
       float lv;
@@ -1620,7 +1626,7 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
         const double th = I.st->theta_cur;
         lv = (float)((th * (double)tk + I.lam * (double)mv) / (I.lam + th));
       }
-      const float old = I.L[t];
+      const float old = lold;
       I.L[t] = lv;
       if (I.prec != kFP32) I.D[t] = lv - old;
       const double d = (double)lv - (double)old;

@@ -1375,23 +1375,27 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
   const int vr = wave * 64 + (lane >> 2), vf = lane & 3;
   gcfloat4* vrow = gc4(a.Vp_lo) + (size_t)(sg * kGroup + vr) * (kp / 8) + vf;
   const size_t vstep = (size_t)16 * (kp / 8);
-  UQ8<2> cr[2];
+  // G (from HBM) is prefetched two chunks ahead in two register slots, V (mostly from
+  // L2) one chunk ahead: chunk q + 2's state is loaded while chunk q is contracted
+  UQ8<2> cr[2][2];  // [slot][part]
   float4 cv0, cv1, cv2, cv3;
-  auto coop_load = [&](int cb) {
+  auto load_g = [&](int cb, int sl) {
     const size_t pidx = ((size_t)lt * 4 + rg) * nkb + cb;
-    load_uq8<2>(I, pidx, 0, lane, cr[0]);
-    load_uq8<2>(I, pidx, 1, lane, cr[1]);
+    load_uq8<2>(I, pidx, 0, lane, cr[sl][0]);
+    load_uq8<2>(I, pidx, 1, lane, cr[sl][1]);
+  };
+  auto load_v = [&](int cb) {
     cv0 = vrow[cb * 4];
     cv1 = vrow[vstep + cb * 4];
     cv2 = vrow[2 * vstep + cb * 4];
     cv3 = vrow[3 * vstep + cb * 4];
   };
-  auto coop_store = [&](int buf, int cb) {
+  auto coop_store = [&](int buf, int cb, int sl) {
     // value v = 4g + e of the tile layout sits at column acc_col(v, hf) = 8g + 4hf + e
     H* gd = Gs + ((size_t)buf * 128 + rg * 32 + (lane & 31)) * kBigLpPad + hf * 4;
     float4 cu[4], cq[4];
-    split_uq8<2>(cr[0], uinv, reinterpret_cast<float4(&)[2]>(cu[0]), reinterpret_cast<float4(&)[2]>(cq[0]));
-    split_uq8<2>(cr[1], uinv, reinterpret_cast<float4(&)[2]>(cu[2]), reinterpret_cast<float4(&)[2]>(cq[2]));
+    split_uq8<2>(cr[sl][0], uinv, reinterpret_cast<float4(&)[2]>(cu[0]), reinterpret_cast<float4(&)[2]>(cq[0]));
+    split_uq8<2>(cr[sl][1], uinv, reinterpret_cast<float4(&)[2]>(cu[2]), reinterpret_cast<float4(&)[2]>(cq[2]));
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const float4 sv = *reinterpret_cast<const float4*>(Ss + cb * 32 + g * 8 + hf * 4);
@@ -1409,30 +1413,43 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
     vd[2 * rs] = cv2;
     vd[3 * rs] = cv3;
   };
-  coop_load(0);
+  load_g(0, 0);
+  load_v(0);
+  load_g(min(1, nkb - 1), 1);
   __syncthreads();
-  coop_store(0, 0);
+  coop_store(0, 0, 0);
   __syncthreads();
-  for (int q = 0; q < nkb; ++q) {
-    const int buf = q & 1;
-    if (q + 1 < nkb) coop_load(q + 1);
-    const H* gb = Gs + ((size_t)buf * 128 + rw * 64 + (lane & 31)) * kBigLpPad + 8 * half;
-    const H* vb = Vs + ((size_t)buf * 256 + sh * 128 + (lane & 31)) * kBigLpPad + 8 * half;
+  // nkb is even (kp is a multiple of 256): chunk q lives in LDS buffer and G slot q & 1
+  for (int q0 = 0; q0 < nkb; q0 += 2) {
 #pragma unroll
-    for (int kk = 0; kk < kBigLpChunk / 16; ++kk) {
-      const V8 g0 = *reinterpret_cast<const V8*>(gb + 16 * kk);
-      const V8 g1 = *reinterpret_cast<const V8*>(gb + 32 * kBigLpPad + 16 * kk);
-      V8 v[4];
+    for (int buf = 0; buf < 2; ++buf) {
+      const int q = q0 + buf;
+      // unconditional (indices clamped; the last chunks reload harmlessly): loads under
+      // a condition would leave the wait counts path-dependent, and the compiler then
+      // waits for every outstanding load, this prefetch included
+      load_v(min(q + 1, nkb - 1));
+      // (V first: loads complete in issue order, so the wait for V(q + 1) before the
+      // end-of-step store must not also wait for the G loads of chunk q + 2)
+      __builtin_amdgcn_sched_barrier(0);
+      load_g(min(q + 2, nkb - 1), buf);  // slot buf held chunk q, already in LDS
+      const H* gb = Gs + ((size_t)buf * 128 + rw * 64 + (lane & 31)) * kBigLpPad + 8 * half;
+      const H* vb = Vs + ((size_t)buf * 256 + sh * 128 + (lane & 31)) * kBigLpPad + 8 * half;
 #pragma unroll
-      for (int sb = 0; sb < 4; ++sb) v[sb] = *reinterpret_cast<const V8*>(vb + sb * 32 * kBigLpPad + 16 * kk);
+      for (int kk = 0; kk < kBigLpChunk / 16; ++kk) {
+        const V8 g0 = *reinterpret_cast<const V8*>(gb + 16 * kk);
+        const V8 g1 = *reinterpret_cast<const V8*>(gb + 32 * kBigLpPad + 16 * kk);
+        V8 v[4];
 #pragma unroll
-      for (int sb = 0; sb < 4; ++sb) {
-        acc[sb][0] = LowP<MODE>::mfma(v[sb], g0, acc[sb][0]);
-        acc[sb][1] = LowP<MODE>::mfma(v[sb], g1, acc[sb][1]);
+        for (int sb = 0; sb < 4; ++sb) v[sb] = *reinterpret_cast<const V8*>(vb + sb * 32 * kBigLpPad + 16 * kk);
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb) {
+          acc[sb][0] = LowP<MODE>::mfma(v[sb], g0, acc[sb][0]);
+          acc[sb][1] = LowP<MODE>::mfma(v[sb], g1, acc[sb][1]);
+        }
       }
+      if (q + 1 < nkb) coop_store(buf ^ 1, q + 1, buf ^ 1);
+      __syncthreads();
     }
-    if (q + 1 < nkb) coop_store(buf ^ 1, q + 1);
-    __syncthreads();
   }
   const int hstride = 128 + 4;
   float* Hs = smem;

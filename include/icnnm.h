@@ -113,6 +113,12 @@ typedef struct {
                         alone with fewer tiles than the chip has compute units: the
                         kernel offsets of a work unit are shared by four wavefronts,
                         which sum in a different order); 0 otherwise */
+  int32_t refresh_x3; /* 1: the refresh iterations of a BF16/FP16 solve ran their
+                         contractions in split BF16 (head + tail of each operand, three
+                         MFMA products, FP32 accumulation) instead of FP32; set where the
+                         tiled adjoint applies (padded k a multiple of 256, 128-row
+                         tiles) unless ICNNM_REFRESH=fp32. A served request reports the
+                         setting of its group when it completed. */
 } icnnm_info;
 
 /* Default parameters: lambda = +inf, theta0 auto, rho 1.1, theta_max 1e10,

@@ -28,6 +28,10 @@ constexpr int kLStepElems = 64; // output elements per L-step workgroup (four la
 enum Phase : int32_t { kNew = 0, kInit = 1, kRun = 2, kDone = 3 };
 
 enum Prec : int32_t { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
+// Kernel mode (not an instance precision): the refresh rounds of BF16/FP16 instances
+// contracted on BF16 MFMA with both operands split into a BF16 head and a BF16 tail
+// (three products: head x head, tail x head, head x tail), FP32 accumulation.
+constexpr int kX3 = 3;
 
 struct alignas(16) InstState {
   double theta;      // penalty for the next iteration (<= 0: derive theta0 at initialisation)
@@ -83,6 +87,8 @@ struct StageArgs {
   const void* Vf_lo;     // forward operand layout of V (BF16/FP16)
   const void* Va_lo;     // adjoint operand layout of V (BF16/FP16)
   const void* Vp_lo;     // V zero-padded to kp x kp, row-major (BF16/FP16)
+  const void* Vf_x;      // split-BF16 V, forward operand layout: heads, then tails
+  const void* Vp_x;      // split-BF16 V, zero-padded row-major: heads, then tails
   int32_t kp, k, nsg, ncg;  // k: offsets of the contraction kernel (innermost extent
                             // padded to a multiple of 4 in BF16/FP16)
   int32_t kt;               // offsets of the kernel itself: the 1/k of the L-step
@@ -94,12 +100,17 @@ struct StageArgs {
   int32_t split;         // split contractions: 64-column (offset) groups, the kernel
                          // offsets (eigendirections) of a unit shared by the four
                          // wavefronts; then ncg = nsg = kp / 64
+  int32_t rx3;           // refresh rounds of BF16/FP16 instances run the kX3 kernels
+                         // (the FP32 kernels then serve only FP32 instances and the
+                         // initialisation)
 };
 
 // Launchers (defined in kernels.hip). All take the stream to launch on.
 void launch_colnorm(const StageArgs& a, int nslices_total, int ninst, hipStream_t st);
 // mode 0: FP32 contraction (initialisation, FP32 solves, refresh iterations);
-// mode 1 / 2: BF16 / FP16 contraction of the change since the previous iteration.
+// mode 1 / 2: BF16 / FP16 contraction of the change since the previous iteration;
+// mode kX3: split-BF16 refresh contraction (forward with 64-row units; adjoint: the
+// tiled one only).
 // gv: col2im gather variant, 0 generic, 8 box lines (innermost kernel extent 4,
 // innermost tile extent 8, E0 E1 <= 512 for every instance of the launch)
 void launch_adjoint(const StageArgs& a, int ntiles_total, int lds_floats, int mode, int gv, hipStream_t st);
@@ -109,8 +120,12 @@ void launch_lstep(const StageArgs& a, int nlblocks_total, hipStream_t st);
 void launch_forward(const StageArgs& a, int ntiles_total, int lds_floats, int mode, int rb, hipStream_t st);
 void launch_prep_v(const float* V, int k, int kp, float* Vf, float* Va, float* Vp, void* Vf_lo,
                    void* Va_lo, void* Vp_lo, int prec, hipStream_t st);
+// split-BF16 copies of V for the kX3 kernels (each kp x kp heads, then kp x kp tails)
+void launch_prep_v_x3(const float* V, int k, int kp, void* Vf_x, void* Vp_x, hipStream_t st);
 // adjoint tiled for large kernels (kp >= 512, 128-row tiles)
 void launch_adjoint_big(const StageArgs& a, int ntiles_total, int mode, int gv, hipStream_t st);
+// LDS bytes of the tiled adjoint's split-BF16 refresh (mode kX3) for padded k = kp
+size_t adjoint_big_x3_lds_bytes(int kp);
 void launch_check_v(const float* V, int k, float* out_maxdev, hipStream_t st);
 // Circular autocorrelation R(d) += sum_x L[x] L[x + d] over the lag box |d_j| < k_j
 // (the Gram of A_k(L) in lag form), tiled: tiles of L with their halo in LDS, partial

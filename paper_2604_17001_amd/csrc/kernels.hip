@@ -63,12 +63,19 @@ struct LowP<kFP16> {
   }
 };
 
+// the split-BF16 refresh contraction uses BF16 MFMA
+template <>
+struct LowP<kX3> : LowP<kBF16> {};
+
 // Which contraction a stage kernel of mode MODE runs for an iterating instance:
-// FP32 on FP32 solves and on refresh iterations, the reduced precision otherwise.
+// FP32 on FP32 solves and on refresh iterations, the reduced precision otherwise;
+// with rx3 set, the refresh iterations of BF16/FP16 instances run the kX3 kernels.
 template <int MODE, class Desc>
-__device__ __forceinline__ bool runs_iteration(const Desc& I, const InstState* st) {
+__device__ __forceinline__ bool runs_iteration(const Desc& I, const InstState* st, int rx3) {
   const bool full = (I.prec == kFP32) || st->refresh;
-  return MODE == kFP32 ? full : (!full && I.prec == MODE);
+  const bool x3 = rx3 && I.prec != kFP32 && st->refresh;
+  if (MODE == kX3) return x3;
+  return MODE == kFP32 ? (full && !x3) : (!full && I.prec == MODE);
 }
 
 // Pointers read from descriptors are generic; loads through them become flat
@@ -322,9 +329,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   const CInstDev& I = *(const CInstDev*)(a.inst + tt.x);
   const int phase = I.st->phase;
   if (MODE == kFP32) {
-    if (phase != kInit && !(phase == kRun && runs_iteration<MODE>(I, I.st))) return;
+    if (phase != kInit && !(phase == kRun && runs_iteration<MODE>(I, I.st, a.rx3))) return;
   } else {
-    if (!(phase == kRun && runs_iteration<MODE>(I, I.st))) return;
+    if (!(phase == kRun && runs_iteration<MODE>(I, I.st, a.rx3))) return;
   }
   const bool init = phase == kInit;
   const int kp = a.kp, k = a.k;
@@ -344,7 +351,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   //       dimension, E4[y][d] = D_halo[y - d] (d < 4), so one 8-byte read yields four
   //       consecutive kernel offsets; offset table offs4[kk*4 + half*2 + g] = off(s)
   //       for s = 16*kk + 8*half + 4*g
-  const int halo_floats = MODE == kFP32 ? ((E123 + 3) & ~3) : 2 * E123;
+  // (split BF16: head, middle and tail parts of L, each an expanded halo)
+  const int halo_floats = MODE == kFP32 ? ((E123 + 3) & ~3) : (MODE == kX3 ? 6 : 2) * E123;
   float* halo = smem;
   int* offs2 = reinterpret_cast<int*>(smem + halo_floats);
   const int noffs = MODE == kFP32 ? kp : kp / 4;
@@ -388,7 +396,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   } else {
     typedef typename LowP<MODE>::h H;
     H* e4 = reinterpret_cast<H*>(halo);
-    gcfloat* D = gc1(I.D);
+    // the delta forms stage D; the split-BF16 refresh stages L in three parts
+    gcfloat* D = gc1(MODE == kX3 ? I.L : I.D);
     // four positions per thread (16 values) are loaded before any is stored, all
     // unconditionally (see the FP32 halo above): excluded entries read a valid
     // address and are set to zero
@@ -416,7 +425,17 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
         const int x = xb + j * kThreads;
         if (x < E123) {
 #pragma unroll
-          for (int d = 0; d < 4; ++d) e4[4 * x + d] = (H)v[j][d];
+          for (int d = 0; d < 4; ++d) {
+            const H hd = (H)v[j][d];
+            e4[4 * x + d] = hd;
+            if constexpr (MODE == kX3) {
+              // v = head + middle + tail + O(2^-27 |v|) (each difference is exact in FP32)
+              const float r = v[j][d] - (float)hd;
+              const H md = (H)r;
+              e4[4 * (E123 + x) + d] = md;
+              e4[4 * (2 * E123 + x) + d] = (H)(r - (float)md);
+            }
+          }
         }
       }
     }
@@ -453,7 +472,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
     // ahead, overlapping the arithmetic and stores of the pieces before it.
     // Split form: the one piece the wavefront finishes is loaded before the contraction.
     constexpr int kPieces = 2 * RB;
-    constexpr bool kEarly = MODE != kFP32 && RB == 2 && !KS;
+    constexpr bool kDelta = MODE == kBF16 || MODE == kFP16;  // W^t = W^{t-1} + delta
+    constexpr bool kEarly = kDelta && RB == 2 && !KS;
     constexpr int kAhead = KS ? 1 : (kEarly ? kPieces : (RB == 4 ? 1 : 2));  // pieces of U/Q loads in flight
     float rsum[kRpu];
 #pragma unroll
@@ -572,50 +592,89 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
     // and the halo buffer it has just consumed, so the loads land in the registers
     // the step read (no copies, exact wait counts). The range [hs0, hs1) has a multiple
     // of kPf steps (kp is a multiple of 64, of 256 in the split form).
-    constexpr int kPf = RB == 4 ? 2 : 4;  // eight MFMAs per step with four row blocks
+    // Split BF16 (kX3): L in three parts (l0 + l1 + l2), V in two (v0 + v1); five
+    // MFMAs per step and block, the small terms first: l1 v1, l2 v0, l0 v1, l1 v0,
+    // l0 v0 (dropped: l2 v1, 2^-27 relative). Splitting L in two parts only leaves a
+    // 2^-18 relative error in each refresh that shows in the solution (W's trailing
+    // eigendirections are small sums of large terms); V's 2^-18 is a fixed
+    // perturbation of V and does not.
+    constexpr bool kX = MODE == kX3;
+    constexpr int kPf = (RB == 4 || kX) ? 2 : 4;  // eight (twenty) MFMAs per step
     typedef typename LowP<MODE>::gv8 GV8;
-    GV8* vf0 = reinterpret_cast<GV8*>(gc4(a.Vf_lo)) + (size_t)(c0 / 32) * nhs * 64 + lane;
+    GV8* vf0 = reinterpret_cast<GV8*>(gc4(kX ? a.Vf_x : a.Vf_lo)) + (size_t)(c0 / 32) * nhs * 64 + lane;
     GV8* vf1 = vf0 + (size_t)nhs * 64;
-    V8 ra[kPf][2];
+    const size_t vtail = (size_t)kp * kp / 8;  // the tails follow the heads (in V8)
+    const V4* e4m = e4 + E123;                 // middle-part halo
+    const V4* e4t = e4 + 2 * E123;             // tail halo
+    V8 ra[kPf][2], rt[kX ? kPf : 1][2];
     V4 bn[2][RB][2];  // [step parity][row block][offset run]
+    V4 bm[kX ? 2 : 1][RB][2], bt[kX ? 2 : 1][RB][2];
     auto load_d = [&](int kk, int slot) {
       const int2 ot = *reinterpret_cast<const int2*>(offs2 + kk * 4 + half * 2);
 #pragma unroll
       for (int ib = 0; ib < RB; ++ib) {
         bn[slot][ib][0] = e4[base[ib] - ot.x];
         bn[slot][ib][1] = e4[base[ib] - ot.y];
+        if constexpr (kX) {
+          bm[slot][ib][0] = e4m[base[ib] - ot.x];
+          bm[slot][ib][1] = e4m[base[ib] - ot.y];
+          bt[slot][ib][0] = e4t[base[ib] - ot.x];
+          bt[slot][ib][1] = e4t[base[ib] - ot.y];
+        }
       }
     };
 #pragma unroll
     for (int i = 0; i < kPf; ++i) {
       ra[i][0] = vf0[(size_t)(hs0 + i) * 64];
       ra[i][1] = vf1[(size_t)(hs0 + i) * 64];
+      if constexpr (kX) {
+        rt[i][0] = vf0[vtail + (size_t)(hs0 + i) * 64];
+        rt[i][1] = vf1[vtail + (size_t)(hs0 + i) * 64];
+      }
     }
     load_d(hs0, 0);
     for (int kb = hs0; kb < hs1; kb += kPf) {
 #pragma unroll
       for (int i = 0; i < kPf; ++i) {
         const int kk = kb + i, cur = i & 1;
-        V8 bv[RB];
+        V8 bv[RB], bmv[kX ? RB : 1], btv[kX ? RB : 1];
 #pragma unroll
         for (int ib = 0; ib < RB; ++ib)
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             bv[ib][j] = bn[cur][ib][0][j];
             bv[ib][4 + j] = bn[cur][ib][1][j];
+            if constexpr (kX) {
+              bmv[ib][j] = bm[cur][ib][0][j];
+              bmv[ib][4 + j] = bm[cur][ib][1][j];
+              btv[ib][j] = bt[cur][ib][0][j];
+              btv[ib][4 + j] = bt[cur][ib][1][j];
+            }
           }
         // the halo reads of the next step go to the other parity buffer
         load_d(min(kk + 1, hs1 - 1), cur ^ 1);
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-          for (int ib = 0; ib < RB; ++ib) acc[cb][ib] = LowP<MODE>::mfma(ra[i][cb], bv[ib], acc[cb][ib]);
+          for (int ib = 0; ib < RB; ++ib) {
+            if constexpr (kX) {
+              acc[cb][ib] = LowP<MODE>::mfma(rt[i][cb], bmv[ib], acc[cb][ib]);
+              acc[cb][ib] = LowP<MODE>::mfma(ra[i][cb], btv[ib], acc[cb][ib]);
+              acc[cb][ib] = LowP<MODE>::mfma(rt[i][cb], bv[ib], acc[cb][ib]);
+              acc[cb][ib] = LowP<MODE>::mfma(ra[i][cb], bmv[ib], acc[cb][ib]);
+            }
+            acc[cb][ib] = LowP<MODE>::mfma(ra[i][cb], bv[ib], acc[cb][ib]);
+          }
         __builtin_amdgcn_sched_barrier(0);
         // unconditional (clamped) refill keeps the body branch-free; the last steps
         // reload the final fragments harmlessly
         const int kn = min(kk + kPf, hs1 - 1);
         ra[i][0] = vf0[(size_t)kn * 64];
         ra[i][1] = vf1[(size_t)kn * 64];
+        if constexpr (kX) {
+          rt[i][0] = vf0[vtail + (size_t)kn * 64];
+          rt[i][1] = vf1[vtail + (size_t)kn * 64];
+        }
       }
     }
     }
@@ -712,7 +771,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
               // residual (Z - W)^2
               const float qo = wo[e] - uo[e];
               float w, unew;
-              if constexpr (MODE != kFP32) {
+              if constexpr (kDelta) {
                 // W^t = W^{t-1} + A_k(L^t - L^{t-1}) V; this form (masking after the
                 // update) schedules better in the HBM-bound reduced-precision kernels
                 w = acc[cb][ib][4 * g + e] + wo[e];
@@ -756,7 +815,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
           }
           // FP32: one piece at a time (keeps the scheduler from hoisting the loads of
           // later pieces, which costs registers)
-          if constexpr (MODE == kFP32) __builtin_amdgcn_sched_barrier(0);
+          if constexpr (!kDelta) __builtin_amdgcn_sched_barrier(0);
           if (KS || (ib & 1)) {  // column partials of one 64-row chunk (32-row block: split)
             int vi;
             const float q = half_sum16(qs, lane, vi);
@@ -1010,7 +1069,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
   // the generic one (with constant fields its per-thread accumulators spill)
   typedef typename std::conditional<GV == 8, const CInstDev, const InstDev>::type Desc;
   Desc& I = *(Desc*)(a.inst + tt.x);
-  if (I.st->phase != kRun || !runs_iteration<MODE>(I, I.st)) return;
+  if (I.st->phase != kRun || !runs_iteration<MODE>(I, I.st, a.rx3)) return;
   const int kp = a.kp, k = a.k;
   const int SGW = KS ? kColUnit : (kp < kGroup ? kp : kGroup);
   const int lt = tt.y;
@@ -1218,7 +1277,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big(StageArgs a) {
   // the generic one (with constant fields its per-thread accumulators spill)
   typedef typename std::conditional<GV == 8, const CInstDev, const InstDev>::type Desc;
   Desc& I = *(Desc*)(a.inst + tt.x);
-  if (I.st->phase != kRun || !runs_iteration<kFP32>(I, I.st)) return;
+  if (I.st->phase != kRun || !runs_iteration<kFP32>(I, I.st, a.rx3)) return;
   const int kp = a.kp, k = a.k;
   const int lt = tt.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5;
@@ -1334,9 +1393,14 @@ constexpr int kBigLpPad = kBigLpChunk + 8;
 // floats of LDS before the shrink factors: the staging buffers or the staged H^T
 constexpr int kBigLpStage = (2 * (128 + 256) * kBigLpPad / 2 > 128 * (128 + 4)) ? 2 * (128 + 256) * kBigLpPad / 2
                                                                                   : 128 * (128 + 4);
+// split-BF16 refresh (MODE kX3): G = U + s.Q formed in FP32 and staged in three BF16
+// parts (g0 + g1 + g2), V in two (v0 + v1); five MFMAs per product, the small terms
+// first: g1 v1, g2 v0, g0 v1, g1 v0, g0 v0 (one workgroup per compute unit)
+constexpr int kBigX3Stage = ((3 * 128 + 2 * 256) * kBigLpPad > 128 * (128 + 4)) ? (3 * 128 + 2 * 256) * kBigLpPad
+                                                                                : 128 * (128 + 4);
 
 template <int MODE, int GV>
-__global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
+__global__ __launch_bounds__(kThreads, MODE == kX3 ? 1 : 2) void k_adjoint_big_lp(StageArgs a) {
   typedef typename LowP<MODE>::h H;
   typedef typename LowP<MODE>::v8 V8;
   typedef typename LowP<MODE>::v4 V4;
@@ -1348,15 +1412,19 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
   // the generic one (with constant fields its per-thread accumulators spill)
   typedef typename std::conditional<GV == 8, const CInstDev, const InstDev>::type Desc;
   Desc& I = *(Desc*)(a.inst + tt.x);
-  if (I.st->phase != kRun || !runs_iteration<MODE>(I, I.st)) return;
+  if (I.st->phase != kRun || !runs_iteration<MODE>(I, I.st, a.rx3)) return;
   const int kp = a.kp, k = a.k;
   const int lt = tt.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5;
   const int nkb = kp / 32;
   const int rw = wave & 1, sh = wave >> 1;
+  constexpr bool kX = MODE == kX3;
   H* Gs = reinterpret_cast<H*>(smem);                  // [2][128][kBigLpPad]
   H* Vs = Gs + 2 * 128 * kBigLpPad;                    // [2][256][kBigLpPad]
-  float* Ss = smem + kBigLpStage;                      // shrink factors [kp]
+  H* Gm = Vs + 2 * 256 * kBigLpPad;                    // kX3: G middle parts [2][128][kBigLpPad]
+  H* Gt = Gm + 2 * 128 * kBigLpPad;                    //      G tails [2][128][kBigLpPad]
+  H* Vt = Gt + 2 * 128 * kBigLpPad;                    //      V tails [2][256][kBigLpPad]
+  float* Ss = smem + (kX ? kBigX3Stage : kBigLpStage);  // shrink factors [kp]
   for (int c = threadIdx.x; c < kp; c += kThreads) Ss[c] = I.s[c];
   GatherAcc<GV, kMaxOwnedBig> gacc;
   gacc.zero();
@@ -1373,12 +1441,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
   // and a quarter (16 bytes) of four V rows of this offset group: instruction i of
   // wavefront w covers rows w * 64 + 16 i .. + 15 whole, 64 contiguous bytes each
   const int vr = wave * 64 + (lane >> 2), vf = lane & 3;
-  gcfloat4* vrow = gc4(a.Vp_lo) + (size_t)(sg * kGroup + vr) * (kp / 8) + vf;
+  gcfloat4* vrow = gc4(kX ? a.Vp_x : a.Vp_lo) + (size_t)(sg * kGroup + vr) * (kp / 8) + vf;
   const size_t vstep = (size_t)16 * (kp / 8);
+  const size_t vtail = (size_t)kp * kp / 8;  // kX3: the tails follow the heads (in float4)
   // G (from HBM) is prefetched two chunks ahead in two register slots, V (mostly from
   // L2) one chunk ahead: chunk q + 2's state is loaded while chunk q is contracted
   UQ8<2> cr[2][2];  // [slot][part]
-  float4 cv0, cv1, cv2, cv3;
+  float4 cv0, cv1, cv2, cv3, ct0, ct1, ct2, ct3;  // ct: kX3 tails
   auto load_g = [&](int cb, int sl) {
     const size_t pidx = ((size_t)lt * 4 + rg) * nkb + cb;
     load_uq8<2>(I, pidx, 0, lane, cr[sl][0]);
@@ -1389,6 +1458,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
     cv1 = vrow[vstep + cb * 4];
     cv2 = vrow[2 * vstep + cb * 4];
     cv3 = vrow[3 * vstep + cb * 4];
+    if constexpr (kX) {
+      ct0 = vrow[vtail + cb * 4];
+      ct1 = vrow[vtail + vstep + cb * 4];
+      ct2 = vrow[vtail + 2 * vstep + cb * 4];
+      ct3 = vrow[vtail + 3 * vstep + cb * 4];
+    }
   };
   auto coop_store = [&](int buf, int cb, int sl) {
     // value v = 4g + e of the tile layout sits at column acc_col(v, hf) = 8g + 4hf + e
@@ -1400,10 +1475,25 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
     for (int g = 0; g < 4; ++g) {
       const float4 sv = *reinterpret_cast<const float4*>(Ss + cb * 32 + g * 8 + hf * 4);
       V4 t;
-      t[0] = (H)((sv.x - 1.f) * cq[g].x - cu[g].x * rp);
-      t[1] = (H)((sv.y - 1.f) * cq[g].y - cu[g].y * rp);
-      t[2] = (H)((sv.z - 1.f) * cq[g].z - cu[g].z * rp);
-      t[3] = (H)((sv.w - 1.f) * cq[g].w - cu[g].w * rp);
+      if constexpr (kX) {
+        const float gv[4] = {cu[g].x + sv.x * cq[g].x, cu[g].y + sv.y * cq[g].y, cu[g].z + sv.z * cq[g].z,
+                             cu[g].w + sv.w * cq[g].w};
+        V4 tm4, tt4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          t[e] = (H)gv[e];
+          const float r = gv[e] - (float)t[e];
+          tm4[e] = (H)r;
+          tt4[e] = (H)(r - (float)tm4[e]);
+        }
+        *reinterpret_cast<V4*>(gd + (Gm - Gs) + 8 * g) = tm4;
+        *reinterpret_cast<V4*>(gd + (Gt - Gs) + 8 * g) = tt4;
+      } else {
+        t[0] = (H)((sv.x - 1.f) * cq[g].x - cu[g].x * rp);
+        t[1] = (H)((sv.y - 1.f) * cq[g].y - cu[g].y * rp);
+        t[2] = (H)((sv.z - 1.f) * cq[g].z - cu[g].z * rp);
+        t[3] = (H)((sv.w - 1.f) * cq[g].w - cu[g].w * rp);
+      }
       *reinterpret_cast<V4*>(gd + 8 * g) = t;
     }
     float4* vd = reinterpret_cast<float4*>(Vs + ((size_t)buf * 256 + vr) * kBigLpPad) + vf;
@@ -1412,6 +1502,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
     vd[rs] = cv1;
     vd[2 * rs] = cv2;
     vd[3 * rs] = cv3;
+    if constexpr (kX) {
+      float4* vtd = vd + (Vt - Vs) / 8;
+      vtd[0] = ct0;
+      vtd[rs] = ct1;
+      vtd[2 * rs] = ct2;
+      vtd[3 * rs] = ct3;
+    }
   };
   load_g(0, 0);
   load_v(0);
@@ -1441,6 +1538,27 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
         V8 v[4];
 #pragma unroll
         for (int sb = 0; sb < 4; ++sb) v[sb] = *reinterpret_cast<const V8*>(vb + sb * 32 * kBigLpPad + 16 * kk);
+        if constexpr (kX) {
+          const H* gmb = gb + (Gm - Gs);
+          const H* gtb = gb + (Gt - Gs);
+          const H* vtb = vb + (Vt - Vs);
+          const V8 m0 = *reinterpret_cast<const V8*>(gmb + 16 * kk);
+          const V8 m1 = *reinterpret_cast<const V8*>(gmb + 32 * kBigLpPad + 16 * kk);
+          const V8 t0 = *reinterpret_cast<const V8*>(gtb + 16 * kk);
+          const V8 t1 = *reinterpret_cast<const V8*>(gtb + 32 * kBigLpPad + 16 * kk);
+#pragma unroll
+          for (int sb = 0; sb < 4; ++sb) {
+            const V8 vt = *reinterpret_cast<const V8*>(vtb + sb * 32 * kBigLpPad + 16 * kk);
+            acc[sb][0] = LowP<MODE>::mfma(vt, m0, acc[sb][0]);
+            acc[sb][1] = LowP<MODE>::mfma(vt, m1, acc[sb][1]);
+            acc[sb][0] = LowP<MODE>::mfma(v[sb], t0, acc[sb][0]);
+            acc[sb][1] = LowP<MODE>::mfma(v[sb], t1, acc[sb][1]);
+            acc[sb][0] = LowP<MODE>::mfma(vt, g0, acc[sb][0]);
+            acc[sb][1] = LowP<MODE>::mfma(vt, g1, acc[sb][1]);
+            acc[sb][0] = LowP<MODE>::mfma(v[sb], m0, acc[sb][0]);
+            acc[sb][1] = LowP<MODE>::mfma(v[sb], m1, acc[sb][1]);
+          }
+        }
 #pragma unroll
         for (int sb = 0; sb < 4; ++sb) {
           acc[sb][0] = LowP<MODE>::mfma(v[sb], g0, acc[sb][0]);
@@ -1909,6 +2027,32 @@ __global__ void k_prep_v_lp(const float* V, int k, int kp, void* Vf_lo, void* Va
   }
 }
 
+// Split-BF16 copies for the kX3 kernels: V = head + tail + O(2^-18 |V|), head = BF16(V),
+// tail = BF16(V - head); the same layouts as Vf_lo and Vp_lo, each array kp x kp heads
+// followed by kp x kp tails.
+__global__ void k_prep_v_x3(const float* V, int k, int kp, __bf16* vf, __bf16* vp) {
+  const int nhs = kp / 16;
+  const int64_t n = (int64_t)kp * kp;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    {
+      const int s = (int)(e / kp), c = (int)(e % kp);
+      const float v = (s < k && c < k) ? V[(int64_t)s * k + c] : 0.f;
+      const __bf16 h = (__bf16)v;
+      vp[e] = h;
+      vp[n + e] = (__bf16)(v - (float)h);
+    }
+    const int j = (int)(e & 7);
+    const int l = (int)((e >> 3) & 63);
+    const int64_t blk = e >> 9;
+    const int kk = (int)(blk % nhs), cb = (int)(blk / nhs);
+    const int s = 16 * kk + 8 * (l >> 5) + j, c = cb * 32 + (l & 31);
+    const float v = (s < k && c < k) ? V[(int64_t)s * k + c] : 0.f;
+    const __bf16 h = (__bf16)v;
+    vf[e] = h;
+    vf[n + e] = (__bf16)(v - (float)h);
+  }
+}
+
 // max_{i,j} |(V^T V - I)_{ij}| with FP64 dot products.
 __global__ void k_check_v(const float* V, int k, float* out) {
   __shared__ float red[kThreads];
@@ -2060,12 +2204,17 @@ static void launch_adjoint_big_gv(const StageArgs& a, int ntiles_total, int mode
       hipLaunchKernelGGL((k_adjoint_big<GV, 2>), g, b, lds * 4, st, a);
     else
       hipLaunchKernelGGL((k_adjoint_big<GV, 4>), g, b, lds * 4, st, a);
+  } else if (mode == kX3) {
+    const int lds = kBigX3Stage + a.kp;
+    hipLaunchKernelGGL((k_adjoint_big_lp<kX3, GV>), g, b, lds * 4, st, a);
   } else {
     const int lds = kBigLpStage + a.kp;
     if (mode == kBF16) hipLaunchKernelGGL((k_adjoint_big_lp<kBF16, GV>), g, b, lds * 4, st, a);
     if (mode == kFP16) hipLaunchKernelGGL((k_adjoint_big_lp<kFP16, GV>), g, b, lds * 4, st, a);
   }
 }
+
+size_t adjoint_big_x3_lds_bytes(int kp) { return (size_t)(kBigX3Stage + kp) * 4; }
 
 void launch_adjoint_big(const StageArgs& a, int ntiles_total, int mode, int gv, hipStream_t st) {
   if (gv == 8)
@@ -2113,7 +2262,9 @@ static void launch_forward_ks(const StageArgs& a, int ntiles_total, int lds_floa
                               hipStream_t st) {
   const dim3 g(ntiles_total, a.ncg), b(kThreads);
   const size_t lds = (size_t)lds_floats * 4;
-  if (mode == kBF16) {
+  if (mode == kX3) {
+    if constexpr (!KS) hipLaunchKernelGGL((k_forward<kX3, 2, 2, false>), g, b, lds, st, a);
+  } else if (mode == kBF16) {
     if (rb == 4 && !KS)
       hipLaunchKernelGGL((k_forward<kBF16, 4, 2, false>), g, b, lds, st, a);
     else
@@ -2143,6 +2294,11 @@ void launch_prep_v(const float* V, int k, int kp, float* Vf, float* Va, float* V
   hipLaunchKernelGGL(k_prep_v, g, b, 0, st, V, k, kp, Vf, Va, Vp);
   if (prec == kBF16) hipLaunchKernelGGL(k_prep_v_lp<kBF16>, g, b, 0, st, V, k, kp, Vf_lo, Va_lo, Vp_lo);
   if (prec == kFP16) hipLaunchKernelGGL(k_prep_v_lp<kFP16>, g, b, 0, st, V, k, kp, Vf_lo, Va_lo, Vp_lo);
+}
+
+void launch_prep_v_x3(const float* V, int k, int kp, void* Vf_x, void* Vp_x, hipStream_t st) {
+  hipLaunchKernelGGL(k_prep_v_x3, dim3(grid_for((int64_t)kp * kp, 4096)), dim3(kThreads), 0, st, V, k, kp,
+                     reinterpret_cast<__bf16*>(Vf_x), reinterpret_cast<__bf16*>(Vp_x));
 }
 
 void launch_check_v(const float* V, int k, float* out, hipStream_t st) {

@@ -131,13 +131,14 @@ static int pow2ceil(int v) {
 // partial sums of the split contractions: 12 slots of one 32x32 accumulator piece
 constexpr int kSplitRedFloats = 12 * 16 * 64;
 
-static int lds_forward_floats(const Plan& p, int kp, bool split = false) {
+static int lds_forward_floats(const Plan& p, int kp, bool split = false, bool x3 = false) {
   // FP32: halo + offset table; reduced precision: 4-wide expanded halo of 16-bit values
-  // (2 floats per position) + a quarter-size offset table; the larger of the two; then
-  // the column and residual partials (and the split form's partial sums)
+  // (2 floats per position; three such halos in the split-BF16 refresh) + a quarter-size
+  // offset table; the larger of the two; then the column and residual partials (and
+  // the split form's partial sums)
   const int CG = split ? kColUnit : std::min(kp, kGroup);
   const int nrc = p.bm / kRowUnit, ncc = CG / kColUnit;
-  const int h32 = ((p.E123 + 3) & ~3) + kp, hlp = 2 * p.E123 + kp / 4;
+  const int h32 = ((p.E123 + 3) & ~3) + kp, hlp = (x3 ? 6 : 2) * p.E123 + kp / 4;
   if (split) return std::max(h32, hlp) + 2 * (2 * nrc) * CG + 4 * nrc * ncc + kSplitRedFloats;
   return std::max(h32, hlp) + 2 * nrc * CG + nrc * ncc;
 }
@@ -380,8 +381,13 @@ struct Group {
   int kp, nsg, ncg, prec;
   const float* Vsrc = nullptr;
   DevBuf Vf, Va, Vp, Vlo_f, Vlo_a, Vlo_p;
+  DevBuf Vx_f, Vx_p;  // split-BF16 V (heads, then tails) for the refresh rounds
   DevBuf Vpad;  // V with the zero rows and columns of padded kernel offsets
   bool big = false;  // adjoint tiled for operand reuse: kp a multiple of 256, 128-row tiles
+  // refresh rounds of the reduced precisions contracted in split BF16 (the tiled adjoint
+  // and the 64-row-unit forward) instead of FP32; ICNNM_REFRESH=fp32 keeps FP32
+  bool rx3 = false;
+  int lds_fwd_x3 = 0;
   bool split = false;  // split contractions: every member's plan has the split form
   std::vector<Member*> members;
   int capacity;
@@ -447,6 +453,11 @@ struct Group {
       Vlo_p.ensure(budget, n * 2);
     }
     launch_prep_v(V, k, kp, Vf.as<float>(), Va.as<float>(), Vp.as<float>(), Vlo_f.p, Vlo_a.p, Vlo_p.p, prec, st);
+    if (prec != kFP32 && kp % kGroup == 0) {  // kp admits the tiled adjoint
+      Vx_f.ensure(budget, n * 4);
+      Vx_p.ensure(budget, n * 4);
+      launch_prep_v_x3(V, k, kp, Vx_f.p, Vx_p.p, st);
+    }
     HIPCK(hipGetLastError());
   }
 
@@ -535,7 +546,7 @@ struct Group {
   void rebuild(hipStream_t st) {
     std::vector<InstDev> ds;
     std::vector<int2> tl, lb, sl;
-    lds_fwd = lds_adj = 0;
+    lds_fwd = lds_adj = lds_fwd_x3 = 0;
     gv = members.empty() ? 0 : 8;
     big = kp % kGroup == 0;
     lp_rb = members.empty() ? 2 : 4;
@@ -553,7 +564,12 @@ struct Group {
       for (int t = 0; t < mb->plan.nslice; ++t) sl.push_back(make_int2((int)i, t));
       lds_fwd = std::max(lds_fwd, lds_forward_floats(mb->plan, kp, split));
       lds_adj = std::max(lds_adj, lds_adjoint_floats(mb->plan, kp, split));
+      lds_fwd_x3 = std::max(lds_fwd_x3, lds_forward_floats(mb->plan, kp, false, true));
     }
+    rx3 = prec != kFP32 && big && !members.empty() && lds_fwd_x3 * 4 <= 150 * 1024 &&
+          adjoint_big_x3_lds_bytes(kp) <= 160 * 1024 && Vx_f.p != nullptr;
+    if (const char* e = getenv("ICNNM_REFRESH"))
+      if (strcmp(e, "fp32") == 0) rx3 = false;
     // ICNNM_GATHER=generic keeps the position-owning gather everywhere (compares the
     // two gathers; every plan's box fits both)
     if (const char* e = getenv("ICNNM_GATHER"))
@@ -595,6 +611,9 @@ struct Group {
     a.Vf_lo = Vlo_f.p;
     a.Va_lo = Vlo_a.p;
     a.Vp_lo = Vlo_p.p;
+    a.Vf_x = Vx_f.p;
+    a.Vp_x = Vx_p.p;
+    a.rx3 = rx3 ? 1 : 0;
     a.kp = kp;
     a.k = k;
     a.kt = kt;
@@ -615,7 +634,8 @@ struct Group {
   void launch_adjoints(const StageArgs& a, hipStream_t st, int only = -1) const {
     const bool f32 = only < 0 || only == kFP32, lo = prec != kFP32 && (only < 0 || only == prec);
     if (big) {
-      if (f32) launch_adjoint_big(a, ntiles_total, kFP32, gv, st);
+      // (with rx3 the FP32 adjoint would serve no instance of this reduced-precision group)
+      if (f32) launch_adjoint_big(a, ntiles_total, rx3 ? kX3 : kFP32, gv, st);
       if (lo) launch_adjoint_big(a, ntiles_total, prec, gv, st);
     } else {
       if (f32) launch_adjoint(a, ntiles_total, lds_adj, kFP32, gv, st);
@@ -629,7 +649,14 @@ struct Group {
     launch_colnorm(a, nslice_total, (int)members.size(), st);
     launch_adjoints(a, st, only);
     launch_lstep(a, nlblk_total, st);
+    launch_forwards(a, st, f32, lo);
+  }
+
+  // FP32 forward (with rx3 only the initialisation), the split-BF16 refresh forward,
+  // the reduced-precision delta forward
+  void launch_forwards(const StageArgs& a, hipStream_t st, bool f32, bool lo) const {
     if (f32) launch_forward(a, ntiles_total, lds_fwd, kFP32, 2, st);
+    if (f32 && rx3) launch_forward(a, ntiles_total, lds_fwd_x3, kX3, 2, st);
     if (lo) launch_forward(a, ntiles_total, lds_fwd, prec, lp_rb, st);
   }
 
@@ -653,8 +680,7 @@ struct Group {
     launch_lstep(a, nlblk_total, st);
     HIPCK(hipEventRecord(prof->ev[5], st));
     HIPCK(hipEventRecord(prof->ev[6], st));
-    if (f32) launch_forward(a, ntiles_total, lds_fwd, kFP32, 2, st);
-    if (lo) launch_forward(a, ntiles_total, lds_fwd, prec, lp_rb, st);
+    launch_forwards(a, st, f32, lo);
     HIPCK(hipEventRecord(prof->ev[7], st));
     HIPCK(hipEventSynchronize(prof->ev[7]));
     const int base = (lo && !f32) ? 4 : 0;
@@ -1184,6 +1210,7 @@ static icnnm_status do_solve(icnnm_ctx* c, const icnnm_shape* shape, const float
   if (info) {
     fill_info(s, info);
     fill_tile(mb->plan, info);
+    info->refresh_x3 = g->rx3 ? 1 : 0;
     info->t_queue_s = 0;
     info->t_device_s = now_s() - t0;
   }
@@ -1257,6 +1284,7 @@ static icnnm_status do_solve_batch(icnnm_ctx* c, int count, const icnnm_shape* s
     if (infos) {
       fill_info(s, &infos[i]);
       fill_tile(mems[i]->plan, &infos[i]);
+      infos[i].refresh_x3 = g.rx3 ? 1 : 0;
       infos[i].t_queue_s = 0;
       infos[i].t_device_s = now_s() - t0;
     }
@@ -1314,6 +1342,7 @@ static size_t noalloc_bytes(const Plan& p, int kp, int prec) {
   b += align256(member_bytes(p, kp, prec));                          // instance state
   b += 3 * align256((size_t)kp * kp * 4);                            // V layouts (FP32)
   if (prec != kFP32) b += 3 * align256((size_t)kp * kp * 2);         // V layouts (16-bit)
+  if (prec != kFP32 && kp % kGroup == 0) b += 2 * align256((size_t)kp * kp * 4);  // split-BF16 V
   b += align256(2 * sizeof(InstDev)) + 3 * align256(2 * 8 * ((size_t)p.ntiles + p.nlblk + p.nslice));  // tables
   return b;
 }
@@ -1387,6 +1416,7 @@ static icnnm_status do_solve_noalloc(icnnm_ctx* c, const icnnm_shape* shape, con
     if (info) {
       fill_info(s, info);
       fill_tile(mb.plan, info);
+      info->refresh_x3 = g.rx3 ? 1 : 0;
       info->t_queue_s = 0;
       info->t_device_s = now_s() - t0;
     }
@@ -1885,6 +1915,7 @@ static void serve_loop(icnnm_ctx* c) {
         d.status = rc != ICNNM_OK ? rc : (s->status != 0 ? ICNNM_E_NUMERIC : ICNNM_OK);
         if (s) fill_info(*s, &d.info);
         fill_tile(mb->plan, &d.info);
+        d.info.refresh_x3 = sg.g->rx3 ? 1 : 0;
         const double t = now_s();
         d.info.t_queue_s = mb->t_start - mb->t_submit;
         d.info.t_device_s = t - mb->t_start;

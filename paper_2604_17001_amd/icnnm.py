@@ -44,7 +44,7 @@ class Info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("r_primal", C.c_double),
                 ("r_change", C.c_double), ("objective", C.c_double), ("theta_final", C.c_double),
                 ("t_queue_s", C.c_double), ("t_device_s", C.c_double), ("tile", C.c_int32 * 3),
-                ("split", C.c_int32)]
+                ("split", C.c_int32), ("refresh_x3", C.c_int32)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -315,7 +315,9 @@ class Library:
     def stage_times(self, reset=True, split=False):
         """{stage: (total_ms, launches)} accumulated while profiling was on; with
         split=True, {(stage, "fp32" | "lowp"): ...}, where "lowp" holds the rounds whose
-        contractions both ran in BF16/FP16."""
+        contractions both ran as BF16/FP16 deltas and "fp32" the others (FP32 solves,
+        initialisation, refresh rounds: FP32 contractions, or split BF16 where the
+        solve's info reports refresh_x3)."""
         ms = (C.c_double * 8)()
         n = (C.c_int64 * 8)()
         rc = self.lib.icnnm_stage_times(self.ctx, ms, n, int(bool(reset)))

@@ -1956,8 +1956,10 @@ static icnnm_status do_submit(icnnm_ctx* c, const icnnm_shape* shape, const floa
   r.bytes = member_bytes(p, kp, params->precision) +
             2 * align256(sizeof(InstDev) + 8 * ((size_t)p.ntiles + p.nlblk + p.nslice));
   // a new group: V operand copies (three FP32 layouts, three more in BF16/FP16 for the
-  // reduced precisions) and the state array of its slots
+  // reduced precisions, and the two split-BF16 ones where kp admits the tiled adjoint)
+  // and the state array of its slots
   r.group_bytes = align256((size_t)kp * kp * 4) * 3 + (params->precision != 0 ? 3 * align256((size_t)kp * kp * 2) : 0) +
+                  (params->precision != 0 && kp % kGroup == 0 ? 2 * align256((size_t)kp * kp * 4) : 0) +
                   align256(sizeof(InstState) * kServeSlots) + (kc != k ? align256((size_t)kc * kc * 4) : 0);
   r.bypassed = 0;
   if (r.bytes + r.group_bytes > c->budget.limit) throw Error(ICNNM_E_BUDGET, "request alone exceeds the HBM budget");

@@ -55,6 +55,7 @@ struct alignas(16) InstDev {
   int32_t m[3], k[3], b[3], E[3], nt[3], C[3], goff[3];
   int32_t ntiles, bm, E123, nlblk, nslice, prec, max_iter, refresh_every;
   int32_t gshift, pad_;  // gather-table entries: (tile << gshift) | box position
+  int32_t lb[3], pad2_;  // log2 of the tile extents b (powers of two)
   int64_t mtot;
   double lam, rho, theta_max, tol, theta0;
   const float* M;

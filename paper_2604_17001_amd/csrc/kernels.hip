@@ -171,10 +171,11 @@ __device__ __forceinline__ int kernel_off(int s, const Desc& I, int k) {
 // that base - off(s) addresses row r's source (forward) or target (adjoint) t = r - s.
 template <class Desc>
 __device__ __forceinline__ int row_base(int r, const Desc& I, const int* o, bool& valid) {
-  int a2 = r % I.b[2];
-  int t = r / I.b[2];
-  int a1 = t % I.b[1];
-  int a0 = t / I.b[1];
+  // tile extents are powers of two: shifts and masks instead of divisions
+  const int a2 = r & (I.b[2] - 1);
+  const int t = r >> I.lb[2];
+  const int a1 = t & (I.b[1] - 1);
+  const int a0 = t >> I.lb[1];
   valid = (o[0] + a0 < I.m[0]) && (o[1] + a1 < I.m[1]) && (o[2] + a2 < I.m[2]);
   return ((a0 + I.k[0] - 1) * I.E[1] + (a1 + I.k[1] - 1)) * I.E[2] + (a2 + I.k[2] - 1);
 }
@@ -457,8 +458,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   const int nun = (nrc / kRpu) * ncc;
   // the kernel-offset half-steps this wavefront contracts
   const int hs0 = KS ? wave * (nhs / 4) : 0, hs1 = KS ? hs0 + nhs / 4 : nhs;
+  // unit u = ru * ncc + cc, advanced without divisions (ncc <= 4)
+  int ru = 0, cc = KS ? 0 : wave;
+  while (cc >= ncc) {
+    cc -= ncc;
+    ++ru;
+  }
   for (int u = KS ? 0 : wave; u < nun; u += KS ? 1 : 4) {
-    const int ru = u / ncc, cc = u % ncc;
     const int c0 = cg * CG + cc * kColUnit;
     bool valid[RB];
     int base[RB];
@@ -843,6 +849,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
       if (lane == 0) rred[KS ? u * 4 + wave : (ru * kRpu + r) * ncc + cc] = rs;
     }
     if constexpr (KS) __syncthreads();  // the partial-sum slots are reused by the next unit
+    cc += KS ? 1 : 4;
+    while (cc >= ncc) {
+      cc -= ncc;
+      ++ru;
+    }
   }
   __syncthreads();
   for (int c = tid; c < CG; c += kThreads) {

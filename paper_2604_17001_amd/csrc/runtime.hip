@@ -481,6 +481,8 @@ struct Group {
       d.m[i] = p.m[i];
       d.k[i] = p.k[i];
       d.b[i] = p.b[i];
+      if (p.b[i] <= 0 || (p.b[i] & (p.b[i] - 1))) throw Error(ICNNM_E_INVALID, "tile extents must be powers of two");
+      d.lb[i] = __builtin_ctz((unsigned)p.b[i]);
       d.E[i] = p.E[i];
       d.nt[i] = p.nt[i];
       d.C[i] = p.C[i];

@@ -339,7 +339,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
   const int cg = blockIdx.y;
   const int CG = KS ? kColUnit : (kp < kGroup ? kp : kGroup);
   const int lt = tt.y;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5;
+  // (the wavefront index is uniform: read into a scalar register, so the unit and
+  // piece indices derived from it stay scalar and hold no vector registers)
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), half = lane >> 5;
 
   int o[3];
   tile_origin(lt, I, o);
@@ -1084,7 +1086,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint(StageArgs a) {
   const int kp = a.kp, k = a.k;
   const int SGW = KS ? kColUnit : (kp < kGroup ? kp : kGroup);
   const int lt = tt.y;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), half = lane >> 5;
   const int bm = I.bm;
   const int nrc = bm / kRowUnit, nsc = SGW / kColUnit;
   const int units = nrc * nsc;
@@ -1291,7 +1293,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_adjoint_big(StageArgs a) {
   if (I.st->phase != kRun || !runs_iteration<kFP32>(I, I.st, a.rx3)) return;
   const int kp = a.kp, k = a.k;
   const int lt = tt.y;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), half = lane >> 5;
   const int nkb = kp / 32;
   const int rw = wave & 1, sh = wave >> 1;             // row chunk, offset half
   float* Gs = smem;                                    // [2][128][kBigPad]
@@ -1426,7 +1428,7 @@ __global__ __launch_bounds__(kThreads, MODE == kX3 ? 1 : 2) void k_adjoint_big_l
   if (I.st->phase != kRun || !runs_iteration<MODE>(I, I.st, a.rx3)) return;
   const int kp = a.kp, k = a.k;
   const int lt = tt.y;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), half = lane >> 5;
   const int nkb = kp / 32;
   const int rw = wave & 1, sh = wave >> 1;
   constexpr bool kX = MODE == kX3;

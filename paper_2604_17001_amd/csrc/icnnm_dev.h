@@ -32,6 +32,9 @@ enum Prec : int32_t { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
 // contracted on BF16 MFMA with both operands split into a BF16 head and a BF16 tail
 // (three products: head x head, tail x head, head x tail), FP32 accumulation.
 constexpr int kX3 = 3;
+// tile ranges per 64-column block in the column-norm reduction (kp / 4 reduction
+// blocks per instance: kp / 64 column blocks x 16 ranges)
+constexpr int kColRanges = 16;
 
 struct alignas(16) InstState {
   double theta;      // penalty for the next iteration (<= 0: derive theta0 at initialisation)
@@ -66,11 +69,12 @@ struct alignas(16) InstDev {
                     // reduced-precision forms (16-byte chunks of eight values)
   float* W;         // A_k(L) V of the current iterate, tile layout, FP32 (Q = W - U)
   float* part;      // adjoint halo partials [ntiles][nsg][E123]
-  float* qpart;     // [ntiles][kp] per-tile sums of Q^2
-  float* wpart;     // [ntiles][kp] per-tile sums of W^2
+  float* qpart;     // [kp / 64][ntiles][64] per-tile sums of Q^2
+  float* wpart;     // [kp / 64][ntiles][64] per-tile sums of W^2
   float* rpart;     // [ntiles][ncg] per-tile sums of (Z - W)^2
   double* dlpart;   // [nlblk][2] L-step partial sums: ||dL||^2, ||P_Omega(L - M)||^2
-  double* slice;    // [2 kp] column sums, then [nslice][3] FP64 slice sums of the scalars
+  double* slice;    // [kColRanges][kp][2] column sums per tile range, then [nslice][3]
+                    // FP64 slice sums of the scalars
   float* s;         // shrink factors [kp]
   float* T;         // reduced precision: running A_k^*(G V^T) / k, updated by deltas  [m]
   const int32_t* gtab;  // per-dimension gather tables, entries (tile << gshift) | position, -1 = none

@@ -864,8 +864,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward(StageArgs a) {
       q += colq[rc * CG + c];
       w += colw[rc * CG + c];
     }
-    I.qpart[(size_t)(cg * CG + c) * I.ntiles + lt] = q;
-    I.wpart[(size_t)(cg * CG + c) * I.ntiles + lt] = w;
+    // blocks of 64 columns, tile-major within a block: each workgroup writes whole
+    // 256-byte runs (column-major over tiles made every value a partial-line write)
+    const int C = cg * CG + c;
+    const size_t pi = ((size_t)(C >> 6) * I.ntiles + lt) * 64 + (C & 63);
+    I.qpart[pi] = q;
+    I.wpart[pi] = w;
   }
   if (tid == 0) {
     float r = 0.f;
@@ -1805,11 +1809,11 @@ __global__ __launch_bounds__(kThreads) void k_lstep(StageArgs a) {
 }
 
 // =====================================================================================
-// colnorm, two launches. k_colnorm_reduce: block b of an instance reduces columns
-// 4b..4b+3 in FP64 (one wavefront per column, lanes over tiles, fixed shuffle tree)
-// and a share of the scalar partials. k_colnorm_finish (one block per instance):
-// column norms -> shrink factors (Z-step), penalty schedule, residuals of the
-// previous iteration, stopping decision, phase changes. The kernel boundary orders
+// colnorm, two launches. k_colnorm_reduce: block b of an instance reduces, in FP64,
+// one tile range of one 64-column block (a lane per column, fixed order) and a share
+// of the scalar partials. k_colnorm_finish (one block per instance): the ranges'
+// column sums in range order, column norms -> shrink factors (Z-step), penalty
+// schedule, residuals of the previous iteration, stopping decision, phase changes. The kernel boundary orders
 // the two, so no device-scope fences or counters are needed.
 // =====================================================================================
 __global__ __launch_bounds__(kThreads) void k_colnorm_reduce(StageArgs a) {
@@ -1820,26 +1824,32 @@ __global__ __launch_bounds__(kThreads) void k_colnorm_reduce(StageArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kp = a.kp;
   const int nt = I.ntiles;
-  double* colsum = I.slice;              // [kp][2]: sum Q^2, sum W^2
-  double* scal = I.slice + 2 * kp;       // [nslice][3]: (Z - W)^2, ||dL||^2, ||P_Omega(L - M)||^2
+  double* colpart = I.slice;             // [kColRanges][kp][2]: sums of Q^2, W^2 per tile range
+  double* scal = I.slice + 2 * kColRanges * kp;  // [nslice][3]: (Z - W)^2, ||dL||^2, ||P_Omega(L - M)||^2
   {
-    const int c = sl.y * 4 + wave;
-    const float* qp = I.qpart + (size_t)c * nt;
-    const float* wp = I.wpart + (size_t)c * nt;
+    // the kp / 4 blocks of an instance: 64-column block cb, tile range r (kColRanges
+    // ranges per column block); lane = column, each wavefront a quarter of the range,
+    // reading whole 256-byte runs of the partials [c / 64][tile][c % 64]
+    const int ncb = kp >> 6;
+    const int cb = sl.y % ncb, r = sl.y / ncb;
+    const int rch = (nt + kColRanges - 1) / kColRanges, wch = (rch + 3) / 4;
+    const int t0 = min(nt, r * rch + wave * wch), t1 = min(min(nt, (r + 1) * rch), t0 + wch);
+    const float* qp = I.qpart + ((size_t)cb * nt) * 64 + lane;
+    const float* wp = I.wpart + ((size_t)cb * nt) * 64 + lane;
     double q = 0.0, w = 0.0;
 #pragma unroll 4
-    for (int t = lane; t < nt; t += 64) {
-      q += (double)qp[t];
-      w += (double)wp[t];
+    for (int t = t0; t < t1; ++t) {
+      q += (double)qp[(size_t)t * 64];
+      w += (double)wp[(size_t)t * 64];
     }
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      q += __shfl_xor(q, o, 64);
-      w += __shfl_xor(w, o, 64);
-    }
-    if (lane == 0) {
-      colsum[2 * c] = q;
-      colsum[2 * c + 1] = w;
+    __shared__ double cred[2][kThreads / 64][64];
+    cred[0][wave][lane] = q;
+    cred[1][wave][lane] = w;
+    __syncthreads();
+    if (wave == 0) {
+      double* d = colpart + 2 * ((size_t)r * kp + cb * 64 + lane);
+      d[0] = ((cred[0][0][lane] + cred[0][1][lane]) + cred[0][2][lane]) + cred[0][3][lane];
+      d[1] = ((cred[1][0][lane] + cred[1][1][lane]) + cred[1][2][lane]) + cred[1][3][lane];
     }
   }
   __shared__ double red[3][kThreads / 64];
@@ -1881,15 +1891,24 @@ __global__ __launch_bounds__(kThreads) void k_colnorm_finish(StageArgs a) {
     return;
   }
   const int kp = a.kp;
-  const double* colsum = I.slice;
-  const double* scal = I.slice + 2 * kp;
+  // column sums: the tile ranges' partials added in range order (the sums land in the
+  // first range's slots, read again below by the thread that wrote them)
+  double* colsum = I.slice;
+  const double* scal = I.slice + 2 * kColRanges * kp;
   __shared__ double sh_obj[kThreads / 64], sh_max[kThreads / 64], sh_rs[kThreads / 64], sh_ds[kThreads / 64],
       sh_pn[kThreads / 64];
   __shared__ double sh_sc[3];
   double obj = 0.0, mx = 0.0, rs = 0.0, ds = 0.0, pn = 0.0;
   for (int c = tid; c < kp; c += kThreads) {
-    obj += sqrt(colsum[2 * c + 1]);
-    mx = fmax(mx, sqrt(colsum[2 * c]));
+    double q = 0.0, w = 0.0;
+    for (int r = 0; r < kColRanges; ++r) {
+      q += colsum[2 * ((size_t)r * kp + c)];
+      w += colsum[2 * ((size_t)r * kp + c) + 1];
+    }
+    colsum[2 * c] = q;
+    colsum[2 * c + 1] = w;
+    obj += sqrt(w);
+    mx = fmax(mx, sqrt(q));
   }
   // slice partials of the residual sums: strided over the block, fixed tree
   for (int j = tid; j < I.nslice; j += kThreads) {

@@ -239,7 +239,7 @@ static void finish_plan(Plan& p, int kp) {
   const int* k = p.k;
   p.mtot = (int64_t)m[0] * m[1] * m[2];
   p.nlblk = (int)((p.mtot + kLStepElems - 1) / kLStepElems);
-  p.nslice = kp / 4;  // column-norm blocks: four columns (one wavefront each) per block
+  p.nslice = kp / 4;  // column-norm blocks: kp / 64 column blocks x kColRanges tile ranges
   // gather tables: for each coordinate t of dimension d, the (tile, box position) pairs
   // whose box position (n b - (k - 1) + p) mod m equals t
   int off = 0;
@@ -356,7 +356,7 @@ static size_t member_bytes(const Plan& p, int kp, int prec) {
   b += 2 * align256((size_t)p.ntiles * kp * 4);              // qpart, wpart
   b += align256((size_t)p.ntiles * ncg * 4);                 // rpart
   b += align256((size_t)p.nlblk * 16);                       // dlpart
-  b += align256((size_t)(2 * kp + 3 * p.nslice) * 8);        // column sums + scalar partials
+  b += align256((size_t)(2 * kColRanges * kp + 3 * p.nslice) * 8);  // column sums + scalar partials
   b += align256((size_t)kp * 4);                             // s
   b += align256(p.gtab.size() * 4);                          // gather tables
   if (prec != kFP32) b += 2 * align256((size_t)p.mtot * 4);  // Lprev, T
@@ -514,7 +514,7 @@ struct Group {
     d.wpart = (float*)take((size_t)p.ntiles * kp * 4);
     d.rpart = (float*)take((size_t)p.ntiles * plan_groups(p, kp) * 4);
     d.dlpart = (double*)take((size_t)p.nlblk * 16);
-    d.slice = (double*)take((size_t)(2 * kp + 3 * p.nslice) * 8);
+    d.slice = (double*)take((size_t)(2 * kColRanges * kp + 3 * p.nslice) * 8);
     d.s = (float*)take((size_t)kp * 4);
     int32_t* gt = (int32_t*)take(p.gtab.size() * 4);
     d.gtab = gt;

@@ -96,9 +96,11 @@ def test_budget_admission_and_rejection():
 
 
 def _group_bytes(kp, prec):
-    """Device bytes a new serving group takes: V operand copies and its slot states."""
+    """Device bytes a new serving group takes: V operand copies (and the split-BF16 ones
+    of a reduced-precision group whose kp admits the tiled adjoint) and its slot states."""
     a = lambda n: (n + 255) // 256 * 256
-    return 3 * a(kp * kp * 4) + (3 * a(kp * kp * 2) if prec != "fp32" else 0) + a(512 * 96)
+    x3 = 2 * a(kp * kp * 4) if prec != "fp32" and kp % 256 == 0 else 0
+    return 3 * a(kp * kp * 4) + (3 * a(kp * kp * 2) if prec != "fp32" else 0) + x3 + a(512 * 96)
 
 
 def test_budget_fits_two_of_six():

@@ -45,6 +45,8 @@ TRAFFIC = {
     ("batch", "bf16", "adjoint"): {"bytes": 13.60e9, "src": "42ed62e05a0372d4"},
     ("128x128x32", "bf16", "forward"): {"bytes": 6.90e9, "src": "42ed62e05a0372d4"},
     ("128x128x32", "bf16", "adjoint"): {"bytes": 4.60e9, "src": "42ed62e05a0372d4"},
+    ("64x64x16", "fp32", "forward"): {"bytes": 0.277e9, "src": "42ed62e05a0372d4"},
+    ("64x64x16", "fp32", "adjoint"): {"bytes": 0.140e9, "src": "42ed62e05a0372d4"},
 }
 
 

@@ -38,6 +38,9 @@
  *    the problem; a different box changes the floating-point summation order,
  *    so results agree to rounding, not bit for bit), and ICNNM_GATHER=generic
  *    keeps the position-owning col2im gather (bit-identical results).
+ *  - Refresh contractions of the BF16/FP16 forms: split BF16 where the tiled
+ *    adjoint applies (icnnm_info.refresh_x3), FP32 MFMA otherwise or with
+ *    ICNNM_REFRESH=fp32 (read when a solve's group is built).
  *  - Thread safety: a context may be used from several host threads; calls
  *    on one context are serialised internally. icnnm_submit/icnnm_poll may be
  *    called concurrently with each other.

@@ -1413,11 +1413,12 @@ constexpr int kBigLpStage = (2 * (128 + 256) * kBigLpPad / 2 > 128 * (128 + 4)) 
 // split-BF16 refresh (MODE kX3): G = U + s.Q formed in FP32 and staged in three BF16
 // parts (g0 + g1 + g2), V in two (v0 + v1); five MFMAs per product, the small terms
 // first: g1 v1, g2 v0, g0 v1, g1 v0, g0 v0 (one workgroup per compute unit)
-constexpr int kBigX3Stage = ((3 * 128 + 2 * 256) * kBigLpPad > 128 * (128 + 4)) ? (3 * 128 + 2 * 256) * kBigLpPad
-                                                                                : 128 * (128 + 4);
+// (single-buffered: two workgroups per CU)
+constexpr int kBigX3Stage = ((3 * 128 + 2 * 256) * kBigLpPad / 2 > 128 * (128 + 4)) ? (3 * 128 + 2 * 256) * kBigLpPad / 2
+                                                                                    : 128 * (128 + 4);
 
 template <int MODE, int GV>
-__global__ __launch_bounds__(kThreads, MODE == kX3 ? 1 : 2) void k_adjoint_big_lp(StageArgs a) {
+__global__ __launch_bounds__(kThreads, 2) void k_adjoint_big_lp(StageArgs a) {
   typedef typename LowP<MODE>::h H;
   typedef typename LowP<MODE>::v8 V8;
   typedef typename LowP<MODE>::v4 V4;
@@ -1436,11 +1437,12 @@ __global__ __launch_bounds__(kThreads, MODE == kX3 ? 1 : 2) void k_adjoint_big_l
   const int nkb = kp / 32;
   const int rw = wave & 1, sh = wave >> 1;
   constexpr bool kX = MODE == kX3;
-  H* Gs = reinterpret_cast<H*>(smem);                  // [2][128][kBigLpPad]
-  H* Vs = Gs + 2 * 128 * kBigLpPad;                    // [2][256][kBigLpPad]
-  H* Gm = Vs + 2 * 256 * kBigLpPad;                    // kX3: G middle parts [2][128][kBigLpPad]
-  H* Gt = Gm + 2 * 128 * kBigLpPad;                    //      G tails [2][128][kBigLpPad]
-  H* Vt = Gt + 2 * 128 * kBigLpPad;                    //      V tails [2][256][kBigLpPad]
+  constexpr int kNB = kX ? 1 : 2;                      // staging buffers
+  H* Gs = reinterpret_cast<H*>(smem);                  // [kNB][128][kBigLpPad]
+  H* Vs = Gs + kNB * 128 * kBigLpPad;                  // [kNB][256][kBigLpPad]
+  H* Gm = Vs + kNB * 256 * kBigLpPad;                  // kX3: G middle parts [1][128][kBigLpPad]
+  H* Gt = Gm + kNB * 128 * kBigLpPad;                  //      G tails [1][128][kBigLpPad]
+  H* Vt = Gt + kNB * 128 * kBigLpPad;                  //      V tails [1][256][kBigLpPad]
   float* Ss = smem + (kX ? kBigX3Stage : kBigLpStage);  // shrink factors [kp]
   for (int c = threadIdx.x; c < kp; c += kThreads) Ss[c] = I.s[c];
   GatherAcc<GV, kMaxOwnedBig> gacc;
@@ -1484,6 +1486,7 @@ __global__ __launch_bounds__(kThreads, MODE == kX3 ? 1 : 2) void k_adjoint_big_l
   };
   auto coop_store = [&](int buf, int cb, int sl) {
     // value v = 4g + e of the tile layout sits at column acc_col(v, hf) = 8g + 4hf + e
+    if constexpr (kX) buf = 0;
     H* gd = Gs + ((size_t)buf * 128 + rg * 32 + (lane & 31)) * kBigLpPad + hf * 4;
     float4 cu[4], cq[4];
     split_uq8<2>(cr[sl][0], uinv, reinterpret_cast<float4(&)[2]>(cu[0]), reinterpret_cast<float4(&)[2]>(cq[0]));
@@ -1546,8 +1549,9 @@ __global__ __launch_bounds__(kThreads, MODE == kX3 ? 1 : 2) void k_adjoint_big_l
       // end-of-step store must not also wait for the G loads of chunk q + 2)
       __builtin_amdgcn_sched_barrier(0);
       load_g(min(q + 2, nkb - 1), buf);  // slot buf held chunk q, already in LDS
-      const H* gb = Gs + ((size_t)buf * 128 + rw * 64 + (lane & 31)) * kBigLpPad + 8 * half;
-      const H* vb = Vs + ((size_t)buf * 256 + sh * 128 + (lane & 31)) * kBigLpPad + 8 * half;
+      const int lb = kX ? 0 : buf;  // LDS buffer of chunk q
+      const H* gb = Gs + ((size_t)lb * 128 + rw * 64 + (lane & 31)) * kBigLpPad + 8 * half;
+      const H* vb = Vs + ((size_t)lb * 256 + sh * 128 + (lane & 31)) * kBigLpPad + 8 * half;
 #pragma unroll
       for (int kk = 0; kk < kBigLpChunk / 16; ++kk) {
         const V8 g0 = *reinterpret_cast<const V8*>(gb + 16 * kk);
@@ -1582,6 +1586,7 @@ __global__ __launch_bounds__(kThreads, MODE == kX3 ? 1 : 2) void k_adjoint_big_l
           acc[sb][1] = LowP<MODE>::mfma(v[sb], g1, acc[sb][1]);
         }
       }
+      if constexpr (kX) __syncthreads();  // single buffer: every wavefront is done with it
       if (q + 1 < nkb) coop_store(buf ^ 1, q + 1, buf ^ 1);
       __syncthreads();
     }

@@ -41,12 +41,12 @@ METRIC = "solved tensors/s at rel.err\u22641e-3 vs FP64 oracle; p50/p99 latency;
 # the same counters on a plain 256 MiB copy (fetch x2.0, write x1.0); valid only for the
 # kernel source they were taken on (sha256 prefix of kernels.hip)
 TRAFFIC = {
-    ("batch", "bf16", "forward"): {"bytes": 27.08e9, "src": "42ed62e05a0372d4"},
-    ("batch", "bf16", "adjoint"): {"bytes": 13.60e9, "src": "42ed62e05a0372d4"},
-    ("128x128x32", "bf16", "forward"): {"bytes": 6.90e9, "src": "42ed62e05a0372d4"},
-    ("128x128x32", "bf16", "adjoint"): {"bytes": 4.60e9, "src": "42ed62e05a0372d4"},
-    ("64x64x16", "fp32", "forward"): {"bytes": 0.277e9, "src": "42ed62e05a0372d4"},
-    ("64x64x16", "fp32", "adjoint"): {"bytes": 0.140e9, "src": "42ed62e05a0372d4"},
+    ("batch", "bf16", "forward"): {"bytes": 27.07e9, "src": "37904d5edc6650ec"},
+    ("batch", "bf16", "adjoint"): {"bytes": 13.60e9, "src": "37904d5edc6650ec"},
+    ("128x128x32", "bf16", "forward"): {"bytes": 6.90e9, "src": "37904d5edc6650ec"},
+    ("128x128x32", "bf16", "adjoint"): {"bytes": 4.60e9, "src": "37904d5edc6650ec"},
+    ("64x64x16", "fp32", "forward"): {"bytes": 0.277e9, "src": "37904d5edc6650ec"},
+    ("64x64x16", "fp32", "adjoint"): {"bytes": 0.140e9, "src": "37904d5edc6650ec"},
 }
 
 

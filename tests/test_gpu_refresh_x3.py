@@ -107,3 +107,38 @@ def test_split_bf16_refresh_several_offset_groups(monkeypatch):
     obs = prob.mask != 0
     assert np.array_equal(Lx[obs], prob.M[obs])
     assert abs(ix["objective"] - if_["objective"]) <= TOL_VS_FP32_REFRESH * if_["objective"]
+
+
+def test_split_bf16_refresh_in_a_batch(monkeypatch):
+    # two instances of different extents in one joint launch: both report the split
+    # refresh and match the same batch with FP32 refreshes
+    from paper_2604_17001_amd import icnnm
+    kd = (8, 8, 4)
+    probs = [inputs.random_problem(d, kd, 0.4, 74 + i) for i, d in enumerate([(32, 32, 16), (32, 16, 16)])]
+    V, _ = O.learn(inputs.random_refs((32, 32, 16), 4, 74), kd)
+    V32 = V.astype(np.float32)
+    monkeypatch.setenv("ICNNM_TILE", "4,4,8")
+    outs = {}
+    for refresh in ("x3", "fp32"):
+        if refresh == "fp32":
+            monkeypatch.setenv("ICNNM_REFRESH", "fp32")
+        else:
+            monkeypatch.delenv("ICNNM_REFRESH", raising=False)
+        print(f"[gpu] split-BF16 refresh batch of 2, refresh {refresh}", flush=True)
+        lib = icnnm.Library()
+        try:
+            Ls, infos = lib.solve_batch([_dev(p.M) for p in probs], [_dev(p.mask) for p in probs], _dev(V32), kd,
+                                        max_iter=40, precision="bf16")
+        finally:
+            lib.close()
+        outs[refresh] = ([L.cpu().numpy() for L in Ls], infos)
+    for i, p in enumerate(probs):
+        Lx, ix = outs["x3"][0][i], outs["x3"][1][i]
+        Lf, if_ = outs["fp32"][0][i], outs["fp32"][1][i]
+        assert ix["refresh_x3"] == 1 and if_["refresh_x3"] == 0
+        d = _rel(Lx, Lf)
+        print(f"[gpu] batch instance {i} dims {p.dims}: split-BF16 against FP32 refresh {d:.3e}", flush=True)
+        assert d <= TOL_VS_FP32_REFRESH
+        obs = p.mask != 0
+        assert np.array_equal(Lx[obs], p.M[obs])
+        assert ix["iters"] == 40
